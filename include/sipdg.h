@@ -1,0 +1,197 @@
+/*
+ * sipdg.h - C ABI of the MI355X SIPG Helmholtz library.
+ *
+ * The library applies, matrix-free, the symmetric interior penalty DG
+ * discretisation of  -lap u + lambda u = s  on unstructured quadrilateral
+ * (2-D) or hexahedral (3-D) spectral elements with per-element polynomial
+ * order (Xia & Moxey, arXiv 2504.03573: Sec. 2.2 eq. IP and eq. primal).
+ * Interfaces between elements of different order are evaluated on a shared
+ * trace space whose Gauss-Lobatto quadrature follows the higher-order side
+ * (Sec. 3.3, "shared trace space"); each side's solution is evaluated at the
+ * trace points and the flux is projected back to the element by the
+ * transposed evaluation, so the operator is symmetric (Appendix A).
+ *
+ * Discretisation fixed by this library (part of the ABI):
+ *   - element e has order p_e in [1, 8], N_P = p_e+1 modes per direction,
+ *     orthogonal (Legendre) basis phi_i = prod_k P_{i_k}(xi_k) with
+ *     P_i(1) = 1 (Table 1, "Orthogonal"), modes lexicographic with the first
+ *     reference direction fastest;
+ *   - tensor Gauss-Lobatto-Legendre quadrature with p_e+2 points per
+ *     direction in the element (Sec. 5.2 benchmark setting), and
+ *     max(p_L,p_R)+2 per direction on an interior face;
+ *   - element map: multilinear from the 2^dim corners, corners stored
+ *     lexicographically (corner with reference coordinates (c_1..c_d) in
+ *     {-1,1}^d at index sum_k ((c_k+1)/2) 2^k);
+ *   - penalty tau_F = sigma * 2 (p_F+1)^2 / h, p_F = max(p_L, p_R) (on a
+ *     boundary face p_e); Dirichlet boundaries by the mirrored exterior
+ *     value u+ = -u- + 2 g, grad u+ = grad u- (Sec. 2.2, boundary values set
+ *     by the boundary condition), hence penalty 2 tau_F on boundary faces.
+ *
+ * Vector layout: natural element order; element e's (p_e+1)^dim
+ * coefficients start at elem_offsets[e].  In a batch, problem after problem.
+ *
+ * Conventions for every function:
+ *   - return 0 (SIPDG_OK) or a negative error code; sipdg_last_error()
+ *     returns a thread-local message for the last failure;
+ *   - "device" pointers are HIP device memory (e.g. torch tensor
+ *     data_ptr()), contiguous, owned by the caller; "host" pointers are
+ *     ordinary memory, read during the call only;
+ *   - stream is a hipStream_t passed as void* (NULL = default stream);
+ *     functions documented "async" only enqueue work on that stream;
+ *   - a handle may be used by one stream at a time.
+ */
+#ifndef SIPDG_H
+#define SIPDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIPDG_OK          0
+#define SIPDG_EINVAL     -1   /* bad argument: null pointer, order out of range, size */
+#define SIPDG_EMESH      -2   /* non-positive Jacobian, face shared by >2 elements,
+                                 faces that do not match by a symmetry of the square */
+#define SIPDG_ENOMEM     -3   /* device or host allocation failed */
+#define SIPDG_EHIP       -4   /* a HIP runtime call failed (no device, launch error) */
+#define SIPDG_ENOCONV    -5   /* CG reached maxit without meeting the tolerance */
+#define SIPDG_EBREAKDOWN -6   /* CG found p^T A p <= 0 (operator not SPD) */
+
+#define SIPDG_F64 0
+#define SIPDG_F32 1
+
+#define SIPDG_MAX_ORDER 8
+
+typedef struct sipdg_ctx *sipdg_handle;
+
+/* One mesh (one problem).  All arrays are host memory, read during create. */
+typedef struct {
+    int dim;                       /* 2 or 3 */
+    int64_t n_vertices;
+    const double *coords;          /* [n_vertices][dim] */
+    int64_t n_elems;
+    const int64_t *elem_vertices;  /* [n_elems][2^dim], lexicographic corners */
+    const int32_t *order;          /* [n_elems], 1..SIPDG_MAX_ORDER */
+    const double *lambda;          /* [n_elems] Helmholtz coefficient per element */
+    double h;                      /* nominal mesh size in tau_F (> 0) */
+    double penalty_scale;          /* sigma in tau_F (> 0) */
+} sipdg_mesh_desc;
+
+/* Mesh statistics computed on the host without a device. */
+typedef struct {
+    int64_t n_elems, n_dofs;
+    int64_t n_interior_faces, n_boundary_faces;
+    int64_t n_nonconforming_faces;   /* interior faces with p_L != p_R */
+    int64_t orientation_count[8];    /* interior faces per orientation code */
+    int64_t n_volume_points, n_trace_points;
+    int64_t elems_per_order[SIPDG_MAX_ORDER + 1];
+} sipdg_mesh_stats;
+
+/* Builds faces (matching by sorted corner ids, owner = lower element id,
+ * orientation of the non-owner side), per-point geometric factors (FP64 and
+ * an FP32 copy rounded once) and the Jacobi diagonal on the current device.
+ * Synchronous.  Errors: EINVAL, EMESH, ENOMEM, EHIP. */
+int sipdg_create(const sipdg_mesh_desc *desc, sipdg_handle *out);
+
+/* Several independent problems in one handle: one vector holds them one
+ * after the other, one launch per kernel covers all of them (elements are
+ * grouped by order across problems), and CG keeps separate scalars and a
+ * separate stopping test per problem. */
+int sipdg_create_batch(int n_problems, const sipdg_mesh_desc *descs, sipdg_handle *out);
+
+void sipdg_destroy(sipdg_handle h);
+
+/* Host-only inspection of a mesh (no device needed).  Same validation and
+ * error codes as sipdg_create. */
+int sipdg_mesh_inspect(const sipdg_mesh_desc *desc, sipdg_mesh_stats *stats);
+
+int sipdg_num_dofs(sipdg_handle h, int64_t *n);
+int sipdg_num_elems(sipdg_handle h, int64_t *n);
+int sipdg_num_problems(sipdg_handle h, int *n);
+/* host [n_elems+1] coefficient offsets of each element */
+int sipdg_elem_offsets(sipdg_handle h, int64_t *off);
+/* host [n_problems+1] coefficient / element offsets of each problem */
+int sipdg_problem_offsets(sipdg_handle h, int64_t *dof_off, int64_t *elem_off);
+
+/* y = A x, async.  precision SIPDG_F64: x, y are double; SIPDG_F32: float,
+ * computed with the FP32 copy of the geometric factors.  x and y must not
+ * overlap.  Scratch (the trace buffer) is owned by the handle. */
+int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *stream);
+
+/* xbar = A^T g, async.  The shared-trace SIPG operator is symmetric, so this
+ * evaluates the same dataflow as sipdg_apply (Appendix A conditions hold by
+ * construction). */
+int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision,
+                          void *stream);
+
+/* d = diag(A) in FP64 (device [n_dofs]), async. */
+int sipdg_diagonal(sipdg_handle h, double *d, void *stream);
+
+/* Gradients of the scalar a^T A b (a, b device FP64 [n_dofs]):
+ * dlambda (device [n_elems]) = (a, b) on each element,
+ * dsigma (device [n_problems]) = sum_F tau_F/sigma ([[a]], [[b]])_F per problem
+ * (boundary faces: 2 a b).  Async. */
+int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *dlambda,
+                     double *dsigma, void *stream);
+
+/* Replace lambda (device FP64 [n_elems]) / sigma (host, per problem or all
+ * when problem < 0).  Refreshes the Jacobi diagonal.  Synchronous. */
+int sipdg_set_lambda(sipdg_handle h, const double *lambda_dev, void *stream);
+int sipdg_set_penalty_scale(sipdg_handle h, int problem, double sigma);
+
+/* Number of volume quadrature points and of boundary trace points. */
+int sipdg_num_points(sipdg_handle h, int64_t *n_volume, int64_t *n_boundary);
+/* Physical coordinates (device FP64, [n][dim]) of the volume quadrature
+ * points (element by element, points lexicographic) and of the boundary
+ * trace points (element by element, boundary faces in local face order
+ * 2k+(s>0), points lexicographic in face coordinates).  Async. */
+int sipdg_quad_points(sipdg_handle h, double *xq, double *xb, void *stream);
+/* b = (phi_i, s) + boundary data terms -(g, grad phi_i . n) + 2 tau (g, phi_i),
+ * from source values s at the volume points and Dirichlet values g at the
+ * boundary points (device FP64).  Async. */
+int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *b,
+                      void *stream);
+
+#define SIPDG_CG_F64     0   /* FP64 Jacobi-PCG */
+#define SIPDG_CG_F32_IR  1   /* FP32 inner PCG inside FP64 iterative refinement */
+
+typedef struct {
+    double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 per problem (1e-10) */
+    int maxit;         /* max total (inner) iterations, per solve */
+    int mode;          /* SIPDG_CG_F64 or SIPDG_CG_F32_IR */
+    double inner_tol;  /* F32_IR: inner relative tolerance (1e-4) */
+    int precond;       /* 1 = Jacobi, 0 = none */
+    int graph_k;       /* iterations per captured HIP graph / per host check; 0 = no graph */
+    int max_outer;     /* F32_IR: max refinement steps (50) */
+    /* optional checkpoint: called every checkpoint_every iterations with the
+     * device pointers of the FP64 iterate x and residual r and the iteration
+     * count; x0_given = 1 starts from the x passed in (resume). */
+    void (*checkpoint)(void *user, const double *x, const double *r, int iter);
+    void *checkpoint_user;
+    int checkpoint_every;
+    int x0_given;
+} sipdg_cg_opts;
+
+typedef struct {
+    int iters;              /* total (inner) iterations */
+    int outer_iters;        /* refinement steps (F32_IR), 1 for F64 */
+    int converged;          /* all problems met tol */
+    double rel_resid;       /* max over problems of true ||b-Ax||/||b|| (FP64) */
+    double time_ms;         /* wall time of the solve */
+} sipdg_cg_info;
+
+void sipdg_cg_default_opts(sipdg_cg_opts *o);
+
+/* Solve A x = b (device FP64 vectors).  Synchronous: returns when done.
+ * Errors: ENOCONV, EBREAKDOWN, EINVAL, EHIP. */
+int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_opts *opts,
+                   sipdg_cg_info *info, void *stream);
+
+const char *sipdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIPDG_H */

@@ -1,0 +1,445 @@
+// C ABI: handle lifetime, operator application, setup products.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "api_common.hpp"
+#include "sipdg.h"
+#include "topology.hpp"
+
+using namespace sipdg;
+
+namespace sipdg {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+template <class T>
+static int dalloc(T **p, int64_t n) {
+    *p = nullptr;
+    if (n <= 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SIPDG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    return SIPDG_OK;
+}
+
+template <class T>
+static int upload(T **p, const std::vector<T> &v) {
+    int rc = dalloc(p, (int64_t)v.size());
+    if (rc) return rc;
+    if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return SIPDG_OK;
+}
+
+template <class R>
+OpArgs<R> make_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *tbuf, const int *skip) {
+    OpArgs<R> A;
+    A.elems = g.d_elems;
+    A.count = g.count;
+    A.tsz = work_size_for(c->dim, g.P, g.nfmax);
+    A.xoff = c->d_xoff;
+    A.voff = c->d_voff;
+    A.eface = c->d_eface;
+    A.foff = c->d_foff;
+    A.toff = c->d_toff;
+    if constexpr (sizeof(R) == 8) {
+        A.vgeo = (const R *)c->d_vgeo64;
+        A.fgeo = (const R *)c->d_fgeo64;
+        A.lam = (const R *)c->d_lam64;
+        A.tau = (const R *)c->d_tau64;
+        A.tab = (const R *)c->d_tab64;
+    } else {
+        A.vgeo = (const R *)c->d_vgeo32;
+        A.fgeo = (const R *)c->d_fgeo32;
+        A.lam = (const R *)c->d_lam32;
+        A.tau = (const R *)c->d_tau32;
+        A.tab = (const R *)c->d_tab32;
+    }
+    A.x = x;
+    A.y = y;
+    A.tbuf = tbuf;
+    A.skip = skip;
+    return A;
+}
+template OpArgs<double> make_args<double>(const sipdg_ctx *, const Group &, const double *, double *, double *, const int *);
+template OpArgs<float> make_args<float>(const sipdg_ctx *, const Group &, const float *, float *, float *, const int *);
+
+template <class R>
+int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st) {
+    for (const Group &g : c->groups) {
+        OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+        hipError_t e = launch_op<R>(c->dim, g.P, OP_TRACE, A, g.nfmax, st);
+        if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
+    }
+    for (const Group &g : c->groups) {
+        OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+        hipError_t e = launch_op<R>(c->dim, g.P, OP_APPLY, A, g.nfmax, st);
+        if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("apply kernel: ") + hipGetErrorString(e));
+    }
+    return SIPDG_OK;
+}
+template int apply_impl<double>(sipdg_ctx *, const double *, double *, double *, const int *, hipStream_t);
+template int apply_impl<float>(sipdg_ctx *, const float *, float *, float *, const int *, hipStream_t);
+
+int refresh_diag(sipdg_ctx *c, hipStream_t st) {
+    hipError_t e = launch_diag(c->dim, c->ne, c->d_order, c->d_xoff, c->d_voff, c->d_eface, c->d_foff,
+                               c->d_vgeo64, c->d_fgeo64, c->d_lam64, c->d_tau64, c->d_tab64,
+                               c->d_diag64, st);
+    if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("diag kernel: ") + hipGetErrorString(e));
+    e = launch_recip(c->d_diag64, c->d_dinv64, c->d_dinv32, c->ndof, st);
+    if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("recip kernel: ") + hipGetErrorString(e));
+    return SIPDG_OK;
+}
+
+static int upload_tau(sipdg_ctx *c) {
+    std::vector<double> tau(c->nfaces);
+    for (int64_t F = 0; F < c->nfaces; ++F) tau[F] = c->sigma[c->face_prob[F]] * c->tau0[F];
+    if (c->nfaces) HIPCHK(hipMemcpy(c->d_tau64, tau.data(), sizeof(double) * c->nfaces, hipMemcpyHostToDevice));
+    hipError_t e = launch_cast_f32(c->d_tau64, c->d_tau32, c->nfaces, 0);
+    if (e != hipSuccess) return fail(SIPDG_EHIP, hipGetErrorString(e));
+    return SIPDG_OK;
+}
+
+}  // namespace sipdg
+
+static void free_ctx(sipdg_ctx *c) {
+    if (!c) return;
+    void *ptrs[] = {c->d_xoff, c->d_voff, c->d_foff, c->d_toff, c->d_qoff, c->d_boff,
+                    c->d_prob_elem_off, c->d_prob_face_off, c->d_prob_dof_off, c->d_eface,
+                    c->d_faces, c->d_order, c->d_is_interior, c->d_face_nf, c->d_flag,
+                    c->d_corners, c->d_tab64, c->d_tab32, c->d_vgeo64, c->d_fgeo64, c->d_lam64,
+                    c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
+                    c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
+                    c->d_dinv64, c->d_dinv32};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (Group &g : c->groups)
+        if (g.d_elems) (void)hipFree(g.d_elems);
+    free_cg(c);
+    delete c;
+}
+
+static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *out) {
+    if (!out) return fail(SIPDG_EINVAL, "null output handle");
+    *out = nullptr;
+    Topology T;
+    std::string err;
+    int rc = build_topology(nprob, descs, T, err);
+    if (rc) return fail(rc, err);
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(SIPDG_EHIP, "no HIP device available");
+    }
+    sipdg_ctx *c = new sipdg_ctx();
+    (void)hipGetDevice(&c->device);
+    c->dim = T.dim;
+    c->nprob = T.nprob;
+    c->ne = T.ne;
+    c->ndof = T.ndof;
+    c->nfaces = T.nfaces;
+    c->nvq = T.qoff[T.ne];
+    c->nbq = T.boff[T.ne];
+    c->vgeo_len = T.vgeo_len;
+    c->fgeo_len = T.fgeo_len;
+    c->tbuf_len = T.tbuf_len;
+    c->order = T.order;
+    c->xoff = T.xoff;
+    c->prob_dof_off = T.prob_dof_off;
+    c->prob_elem_off = T.prob_elem_off;
+    c->prob_face_off = T.prob_face_off;
+    c->tau0 = T.tau0;
+    c->sigma = T.sigma;
+    c->face_prob = T.face_prob;
+
+#define TRY(x)                 \
+    do {                       \
+        int _r = (x);          \
+        if (_r) {              \
+            free_ctx(c);       \
+            return _r;         \
+        }                      \
+    } while (0)
+#define TRYHIP(x)                                                                        \
+    do {                                                                                 \
+        hipError_t _e = (x);                                                             \
+        if (_e != hipSuccess) {                                                          \
+            free_ctx(c);                                                                 \
+            return fail(SIPDG_EHIP, std::string(#x) + ": " + hipGetErrorString(_e));     \
+        }                                                                                \
+    } while (0)
+
+    TRY(upload(&c->d_xoff, T.xoff));
+    TRY(upload(&c->d_voff, T.voff));
+    TRY(upload(&c->d_foff, T.foff));
+    TRY(upload(&c->d_toff, T.toff));
+    TRY(upload(&c->d_qoff, T.qoff));
+    TRY(upload(&c->d_boff, T.boff));
+    TRY(upload(&c->d_prob_elem_off, T.prob_elem_off));
+    TRY(upload(&c->d_prob_face_off, T.prob_face_off));
+    TRY(upload(&c->d_prob_dof_off, T.prob_dof_off));
+    TRY(upload(&c->d_eface, T.eface));
+    TRY(upload(&c->d_faces, T.faces));
+    TRY(upload(&c->d_order, T.order));
+    TRY(upload(&c->d_corners, T.corners));
+    TRY(upload(&c->d_tau0, T.tau0));
+    {
+        std::vector<int> interior(T.nfaces), nf(T.nfaces);
+        for (int64_t F = 0; F < T.nfaces; ++F) {
+            interior[F] = T.faces[F].eR >= 0;
+            nf[F] = T.faces[F].nf;
+        }
+        TRY(upload(&c->d_is_interior, interior));
+        TRY(upload(&c->d_face_nf, nf));
+    }
+    {
+        std::vector<double> tab(TAB_SIZE);
+        build_tables(tab.data());
+        TRY(upload(&c->d_tab64, tab));
+        TRY(dalloc(&c->d_tab32, TAB_SIZE));
+        TRYHIP(launch_cast_f32(c->d_tab64, c->d_tab32, TAB_SIZE, 0));
+    }
+    TRY(dalloc(&c->d_flag, 1));
+    TRYHIP(hipMemset(c->d_flag, 0, sizeof(int)));
+    TRY(dalloc(&c->d_vgeo64, T.vgeo_len));
+    TRY(dalloc(&c->d_fgeo64, T.fgeo_len));
+    TRY(dalloc(&c->d_vgeo32, T.vgeo_len));
+    TRY(dalloc(&c->d_fgeo32, T.fgeo_len));
+    TRYHIP(launch_geo_volume(c->dim, c->ne, c->d_corners, c->d_order, c->d_voff, c->d_tab64, c->d_vgeo64, c->d_flag, 0));
+    TRYHIP(launch_geo_faces(c->dim, c->nfaces, c->d_corners, c->d_faces, c->d_foff, c->d_tab64, c->d_fgeo64, c->d_flag, 0));
+    TRYHIP(launch_cast_f32(c->d_vgeo64, c->d_vgeo32, T.vgeo_len, 0));
+    TRYHIP(launch_cast_f32(c->d_fgeo64, c->d_fgeo32, T.fgeo_len, 0));
+    int flag = 0;
+    TRYHIP(hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+        free_ctx(c);
+        return fail(SIPDG_EMESH, "non-positive Jacobian at a quadrature point");
+    }
+    TRY(upload(&c->d_lam64, T.lambda));
+    TRY(dalloc(&c->d_lam32, T.ne));
+    TRYHIP(launch_cast_f32(c->d_lam64, c->d_lam32, T.ne, 0));
+    TRY(dalloc(&c->d_tau64, T.nfaces));
+    TRY(dalloc(&c->d_tau32, T.nfaces));
+    TRY(upload_tau(c));
+    TRY(dalloc(&c->d_tbuf, T.tbuf_len));
+
+    // order groups, each with the largest trace that touches it
+    for (int P = 1; P <= PMAX; ++P) {
+        std::vector<int> ids;
+        int nfmax = P + 2;
+        for (int64_t e = 0; e < T.ne; ++e) {
+            if (T.order[e] != P) continue;
+            ids.push_back((int)e);
+            for (int f = 0; f < 2 * T.dim; ++f) nfmax = std::max(nfmax, face_nf(T.eface[(size_t)e * 2 * T.dim + f].info));
+        }
+        if (ids.empty()) continue;
+        Group g;
+        g.P = P;
+        g.count = (int)ids.size();
+        g.nfmax = nfmax;
+        g.d_elems = nullptr;
+        TRY(upload(&g.d_elems, ids));
+        c->groups.push_back(g);
+        // check the block fits in LDS
+        hipDeviceProp_t prop;
+        TRYHIP(hipGetDeviceProperties(&prop, c->device));
+        size_t need = lds_for(T.dim, P, work_size_for(T.dim, P, nfmax), true, sizeof(double));
+        size_t limit = prop.sharedMemPerBlock;
+        if (prop.maxSharedMemoryPerMultiProcessor > limit) limit = prop.maxSharedMemoryPerMultiProcessor;
+        if (need > limit) {
+            free_ctx(c);
+            return fail(SIPDG_EINVAL, "order " + std::to_string(P) + " needs " + std::to_string(need) +
+                                          " bytes of LDS per block, device allows " + std::to_string(limit));
+        }
+    }
+    TRY(dalloc(&c->d_diag64, T.ndof));
+    TRY(dalloc(&c->d_dinv64, T.ndof));
+    TRY(dalloc(&c->d_dinv32, T.ndof));
+    TRY(refresh_diag(c, 0));
+    TRYHIP(hipDeviceSynchronize());
+#undef TRY
+#undef TRYHIP
+    *out = c;
+    return SIPDG_OK;
+}
+
+extern "C" {
+
+int sipdg_create(const sipdg_mesh_desc *desc, sipdg_handle *out) {
+    if (!desc) return fail(SIPDG_EINVAL, "null mesh description");
+    return create_impl(1, desc, out);
+}
+
+int sipdg_create_batch(int n_problems, const sipdg_mesh_desc *descs, sipdg_handle *out) {
+    if (n_problems <= 0 || !descs) return fail(SIPDG_EINVAL, "need at least one problem");
+    return create_impl(n_problems, descs, out);
+}
+
+void sipdg_destroy(sipdg_handle h) {
+    if (h) {
+        (void)hipDeviceSynchronize();
+        free_ctx(h);
+    }
+}
+
+int sipdg_mesh_inspect(const sipdg_mesh_desc *desc, sipdg_mesh_stats *st) {
+    if (!desc || !st) return fail(SIPDG_EINVAL, "null argument");
+    Topology T;
+    std::string err;
+    int rc = build_topology(1, desc, T, err);
+    if (rc) return fail(rc, err);
+    std::memset(st, 0, sizeof(*st));
+    st->n_elems = T.ne;
+    st->n_dofs = T.ndof;
+    st->n_interior_faces = T.n_interior;
+    st->n_boundary_faces = T.n_boundary;
+    st->n_nonconforming_faces = T.n_nonconf;
+    for (int o = 0; o < 8; ++o) st->orientation_count[o] = T.orient_count[o];
+    st->n_volume_points = T.qoff[T.ne];
+    st->n_trace_points = T.n_trace_points;
+    for (int64_t e = 0; e < T.ne; ++e) st->elems_per_order[T.order[e]]++;
+    return SIPDG_OK;
+}
+
+int sipdg_num_dofs(sipdg_handle h, int64_t *n) {
+    if (!h || !n) return fail(SIPDG_EINVAL, "null argument");
+    *n = h->ndof;
+    return SIPDG_OK;
+}
+
+int sipdg_num_elems(sipdg_handle h, int64_t *n) {
+    if (!h || !n) return fail(SIPDG_EINVAL, "null argument");
+    *n = h->ne;
+    return SIPDG_OK;
+}
+
+int sipdg_num_problems(sipdg_handle h, int *n) {
+    if (!h || !n) return fail(SIPDG_EINVAL, "null argument");
+    *n = h->nprob;
+    return SIPDG_OK;
+}
+
+int sipdg_elem_offsets(sipdg_handle h, int64_t *off) {
+    if (!h || !off) return fail(SIPDG_EINVAL, "null argument");
+    std::memcpy(off, h->xoff.data(), sizeof(int64_t) * (h->ne + 1));
+    return SIPDG_OK;
+}
+
+int sipdg_problem_offsets(sipdg_handle h, int64_t *dof_off, int64_t *elem_off) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (dof_off) std::memcpy(dof_off, h->prob_dof_off.data(), sizeof(int64_t) * (h->nprob + 1));
+    if (elem_off) std::memcpy(elem_off, h->prob_elem_off.data(), sizeof(int64_t) * (h->nprob + 1));
+    return SIPDG_OK;
+}
+
+int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *stream) {
+    if (!h || !x || !y) return fail(SIPDG_EINVAL, "null argument");
+    if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == SIPDG_F64)
+        return apply_impl<double>(h, (const double *)x, (double *)y, h->d_tbuf, nullptr, st);
+    if (precision == SIPDG_F32)
+        return apply_impl<float>(h, (const float *)x, (float *)y, (float *)h->d_tbuf, nullptr, st);
+    return fail(SIPDG_EINVAL, "precision must be SIPDG_F64 or SIPDG_F32");
+}
+
+int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision, void *stream) {
+    return sipdg_apply(h, g, xbar, precision, stream);
+}
+
+int sipdg_diagonal(sipdg_handle h, double *d, void *stream) {
+    if (!h || !d) return fail(SIPDG_EINVAL, "null argument");
+    HIPCHK(hipMemcpyAsync(d, h->d_diag64, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SIPDG_OK;
+}
+
+int sipdg_set_lambda(sipdg_handle h, const double *lam, void *stream) {
+    if (!h || !lam) return fail(SIPDG_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(h->d_lam64, lam, sizeof(double) * h->ne, hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_cast_f32(h->d_lam64, h->d_lam32, h->ne, st));
+    int rc = refresh_diag(h, st);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(st));
+    return SIPDG_OK;
+}
+
+int sipdg_set_penalty_scale(sipdg_handle h, int problem, double sigma) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (!(sigma > 0.0)) return fail(SIPDG_EINVAL, "penalty scale must be positive");
+    if (problem >= h->nprob) return fail(SIPDG_EINVAL, "problem index out of range");
+    for (int p = 0; p < h->nprob; ++p)
+        if (problem < 0 || p == problem) h->sigma[p] = sigma;
+    HIPCHK(hipDeviceSynchronize());
+    int rc = upload_tau(h);
+    if (rc) return rc;
+    rc = refresh_diag(h, 0);
+    if (rc) return rc;
+    HIPCHK(hipDeviceSynchronize());
+    return SIPDG_OK;
+}
+
+int sipdg_num_points(sipdg_handle h, int64_t *nv, int64_t *nb) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (nv) *nv = h->nvq;
+    if (nb) *nb = h->nbq;
+    return SIPDG_OK;
+}
+
+int sipdg_quad_points(sipdg_handle h, double *xq, double *xb, void *stream) {
+    if (!h || !xq || (!xb && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
+    HIPCHK(launch_points(h->dim, h->ne, h->d_corners, h->d_order, h->d_eface, h->d_qoff, h->d_boff,
+                         h->d_tab64, xq, xb, (hipStream_t)stream));
+    return SIPDG_OK;
+}
+
+int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *b, void *stream) {
+    if (!h || !s || !b || (!g && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
+    for (const Group &gr : h->groups) {
+        OpArgs<double> A = make_args<double>(h, gr, nullptr, b, nullptr, nullptr);
+        A.tsz = work_size_for(h->dim, gr.P, gr.P + 2);
+        HIPCHK(launch_load(h->dim, gr.P, A, h->d_qoff, h->d_boff, s, g, (hipStream_t)stream));
+    }
+    return SIPDG_OK;
+}
+
+int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *dlam, double *dsig,
+                     void *stream) {
+    if (!h || !a || !b || !dlam || !dsig) return fail(SIPDG_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (!h->d_tbuf2) {
+        HIPCHK(hipMalloc((void **)&h->d_tbuf2, sizeof(double) * std::max<int64_t>(1, h->tbuf_len)));
+        HIPCHK(hipMalloc((void **)&h->d_face_tmp, sizeof(double) * std::max<int64_t>(1, h->nfaces)));
+        HIPCHK(hipMalloc((void **)&h->d_elem_tmp, sizeof(double) * std::max<int64_t>(1, h->ne)));
+    }
+    for (const Group &g : h->groups) {
+        OpArgs<double> A = make_args<double>(h, g, a, nullptr, h->d_tbuf, nullptr);
+        HIPCHK(launch_op<double>(h->dim, g.P, OP_TRACE, A, g.nfmax, st));
+        A = make_args<double>(h, g, b, nullptr, h->d_tbuf2, nullptr);
+        HIPCHK(launch_op<double>(h->dim, g.P, OP_TRACE, A, g.nfmax, st));
+        A = make_args<double>(h, g, nullptr, nullptr, nullptr, nullptr);
+        A.tsz = work_size_for(h->dim, g.P, g.P + 2);
+        HIPCHK(launch_pgrad_elem(h->dim, g.P, A, a, b, h->d_tau0, dlam, h->d_elem_tmp, st));
+    }
+    HIPCHK(launch_pgrad_faces(h->dim, h->nfaces, h->d_is_interior, h->d_toff, h->d_foff, h->d_face_nf,
+                              h->d_fgeo64, h->d_tau0, h->d_tbuf, h->d_tbuf2, h->d_face_tmp, st));
+    HIPCHK(launch_segsum(h->nprob, h->d_prob_face_off, h->d_face_tmp, dsig, 0, st));
+    HIPCHK(launch_segsum(h->nprob, h->d_prob_elem_off, h->d_elem_tmp, dsig, 1, st));
+    return SIPDG_OK;
+}
+
+const char *sipdg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

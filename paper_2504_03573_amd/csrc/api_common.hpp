@@ -1,0 +1,33 @@
+// Helpers shared by the host translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "context.hpp"
+#include "launch.hpp"
+
+namespace sipdg {
+
+int fail(int code, const std::string &msg);
+
+#define HIPCHK(call)                                                                         \
+    do {                                                                                     \
+        hipError_t _e = (call);                                                              \
+        if (_e != hipSuccess) {                                                              \
+            (void)hipGetLastError();                                                         \
+            return ::sipdg::fail(SIPDG_EHIP, std::string(#call) + ": " + hipGetErrorString(_e)); \
+        }                                                                                    \
+    } while (0)
+
+template <class R>
+OpArgs<R> make_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *tbuf, const int *skip);
+
+template <class R>
+int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st);
+
+int refresh_diag(sipdg_ctx *c, hipStream_t st);
+void free_cg(sipdg_ctx *c);
+
+}  // namespace sipdg

@@ -1,0 +1,105 @@
+// Library-internal state of one handle and the kernel argument blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tables.hpp"
+
+namespace sipdg {
+
+// Packed description of one local face of an element, as seen by kernels:
+//   x = global face id F
+//   y = slot | orient << 2 | NF << 5
+// slot 0: this element owns F (lower id), 1: the other side, 2: boundary.
+// orient: map between the owner's face coordinates (canonical trace order)
+// and this side's (bit0 flip first, bit1 flip second, bit2 swap).
+// NF: GLL points per direction on the shared trace.
+struct FaceRef {
+    int F;
+    int info;
+};
+
+__host__ __device__ inline int face_slot(int info) { return info & 3; }
+__host__ __device__ inline int face_orient(int info) { return (info >> 2) & 7; }
+__host__ __device__ inline int face_nf(int info) { return (info >> 5) & 31; }
+
+// Own face coordinates (r1, r2) on a trace with nf points per direction ->
+// canonical (owner) index.
+__host__ __device__ inline int canon_index(int orient, int nf, int r1, int r2) {
+    int a1 = (orient & 1) ? nf - 1 - r1 : r1;
+    int a2 = (orient & 2) ? nf - 1 - r2 : r2;
+    return (orient & 4) ? (a2 + nf * a1) : (a1 + nf * a2);
+}
+
+template <class R>
+struct OpArgs {
+    const int *elems;       // element ids of this order group
+    int count;
+    int tsz;                // per-element work-area size (R units)
+    const int64_t *xoff;    // [ne+1] coefficient offsets
+    const int64_t *voff;    // [ne] volume-factor offsets
+    const FaceRef *eface;   // [ne][2 dim]
+    const int64_t *foff;    // [nf] face-factor offsets
+    const int64_t *toff;    // [nf] trace-buffer offsets (-1 on boundary faces)
+    const R *vgeo;          // volume factors
+    const R *fgeo;          // face factors
+    const R *lam;           // [ne]
+    const R *tau;           // [nf] penalty tau_F
+    const R *tab;           // 1-D tables
+    const R *x;
+    R *y;
+    R *tbuf;                // trace buffer
+    const int *skip;        // optional: return at once when *skip != 0
+};
+
+struct Group {
+    int P;
+    int count;
+    int nfmax;              // largest trace size touching the group
+    int *d_elems;
+};
+
+struct CgWork;  // defined in the solver
+struct FaceTopo;
+
+}  // namespace sipdg
+
+struct sipdg_ctx {
+    int dim = 0;
+    int nprob = 0;
+    int device = 0;
+    int64_t ne = 0, ndof = 0, nfaces = 0;
+    int64_t nvq = 0, nbq = 0;          // volume / boundary points
+    int64_t vgeo_len = 0, fgeo_len = 0, tbuf_len = 0;
+
+    // host copies (topology)
+    std::vector<int> order;
+    std::vector<int64_t> xoff, prob_dof_off, prob_elem_off, prob_face_off;
+    std::vector<double> tau0, sigma;
+    std::vector<int> face_prob;
+
+    // device
+    int64_t *d_xoff = nullptr, *d_voff = nullptr, *d_foff = nullptr, *d_toff = nullptr;
+    int64_t *d_qoff = nullptr, *d_boff = nullptr;
+    int64_t *d_prob_elem_off = nullptr, *d_prob_face_off = nullptr, *d_prob_dof_off = nullptr;
+    sipdg::FaceRef *d_eface = nullptr;
+    sipdg::FaceTopo *d_faces = nullptr;
+    int *d_order = nullptr, *d_is_interior = nullptr, *d_face_nf = nullptr, *d_flag = nullptr;
+    double *d_corners = nullptr;
+    double *d_tab64 = nullptr;
+    float *d_tab32 = nullptr;
+    double *d_vgeo64 = nullptr, *d_fgeo64 = nullptr, *d_lam64 = nullptr, *d_tau64 = nullptr;
+    float *d_vgeo32 = nullptr, *d_fgeo32 = nullptr, *d_lam32 = nullptr, *d_tau32 = nullptr;
+    double *d_tau0 = nullptr;
+    double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it
+    double *d_tbuf2 = nullptr;             // second trace buffer (gradients), lazy
+    double *d_face_tmp = nullptr, *d_elem_tmp = nullptr;  // lazy
+    double *d_diag64 = nullptr, *d_dinv64 = nullptr;
+    float *d_dinv32 = nullptr;
+    std::vector<sipdg::Group> groups;
+    sipdg::CgWork *cg = nullptr;
+};

@@ -1,0 +1,52 @@
+// Host-side launchers (implemented next to their kernels).
+#pragma once
+
+#include "context.hpp"
+
+namespace sipdg {
+
+enum OpKind { OP_TRACE = 0, OP_APPLY = 1 };
+
+// Operator kernels for one order group.  tsz must be work_size(nfm).
+template <class R>
+hipError_t launch_op(int dim, int P, int kind, const OpArgs<R> &A, int nfm, hipStream_t st);
+int work_size_for(int dim, int P, int nfm);
+size_t lds_for(int dim, int P, int tsz, bool lift, size_t rsize);
+int elems_per_block(int dim, int P);
+
+hipError_t launch_load(int dim, int P, const OpArgs<double> &A, const int64_t *qoff,
+                       const int64_t *boff, const double *src, const double *gdir,
+                       hipStream_t st);
+hipError_t launch_pgrad_elem(int dim, int P, const OpArgs<double> &A, const double *a,
+                             const double *b, const double *tau0, double *dlam, double *bsig,
+                             hipStream_t st);
+
+// Setup and auxiliary kernels (aux.hip).
+struct FaceTopo {
+    int eL, fL, eR, fR, orient, nf;
+};
+hipError_t launch_geo_volume(int dim, int64_t ne, const double *corners, const int *order,
+                             const int64_t *voff, const double *tab, double *vgeo, int *flag,
+                             hipStream_t st);
+hipError_t launch_geo_faces(int dim, int64_t nfaces, const double *corners, const FaceTopo *ft,
+                            const int64_t *foff, const double *tab, double *fgeo, int *flag,
+                            hipStream_t st);
+hipError_t launch_points(int dim, int64_t ne, const double *corners, const int *order,
+                         const FaceRef *eface, const int64_t *qoff, const int64_t *boff,
+                         const double *tab, double *xq, double *xb, hipStream_t st);
+hipError_t launch_diag(int dim, int64_t ne, const int *order, const int64_t *xoff,
+                       const int64_t *voff, const FaceRef *eface, const int64_t *foff,
+                       const double *vgeo, const double *fgeo, const double *lam,
+                       const double *tau, const double *tab, double *diag, hipStream_t st);
+hipError_t launch_pgrad_faces(int dim, int64_t nfaces, const int *is_interior,
+                              const int64_t *toff, const int64_t *foff, const int *nf,
+                              const double *fgeo, const double *tau0, const double *ta,
+                              const double *tb, double *out, hipStream_t st);
+// out[p] = sum_{i in [off[p], off[p+1])} v[i]  (fixed-order, deterministic)
+hipError_t launch_segsum(int nseg, const int64_t *off, const double *v, double *out, int accumulate,
+                         hipStream_t st);
+hipError_t launch_cast_f32(const double *in, float *out, int64_t n, hipStream_t st);
+hipError_t launch_cast_f64(const float *in, double *out, int64_t n, hipStream_t st);
+hipError_t launch_recip(const double *in, double *out64, float *out32, int64_t n, hipStream_t st);
+
+}  // namespace sipdg

@@ -1,0 +1,55 @@
+// Krylov solver internals: device-side per-problem scalars and the vector
+// kernels' launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sipdg {
+
+// Block decomposition of a (batched) vector: block b covers
+// [blk_start[b], blk_start[b+1]) inside problem blk_prob[b]; problem p owns
+// blocks [prob_blk[p], prob_blk[p+1]).
+struct VecCtx {
+    int nblk;
+    int nprob;
+    const int64_t *blk_start;
+    const int *blk_prob;
+    const int *prob_blk;
+    int *done;   // set once every problem has stopped; kernels then return at once
+};
+
+// Per-problem recurrence scalars (device arrays of length nprob).
+struct CgScalars {
+    double *rho, *alpha, *beta, *bnorm, *rel;
+    int *conv;      // 0 running, 1 converged, 2 breakdown
+    int *iters;     // iterations per problem
+    int *counter;   // [1] iterations executed by the whole batch
+    int *flags;     // [1] bit 1: breakdown seen
+};
+
+template <class R>
+hipError_t vec_dot(const VecCtx &V, const R *a, const R *b, double *partial, hipStream_t st);
+template <class R>
+hipError_t vec_update(const VecCtx &V, const CgScalars &S, R *x, R *r, const R *p, const R *q,
+                      const R *dinv, R *z, double *prr, double *prz, hipStream_t st);
+template <class R>
+hipError_t vec_pupdate(const VecCtx &V, const CgScalars &S, const R *z, R *p, hipStream_t st);
+template <class R>
+hipError_t vec_start(const VecCtx &V, const R *r, const R *dinv, R *z, R *p, R *x, double *prr,
+                     double *prz, hipStream_t st);
+template <class R>
+hipError_t vec_fill(R *v, int64_t n, R val, hipStream_t st);
+hipError_t vec_fin_alpha(const VecCtx &V, const CgScalars &S, const double *ppq, hipStream_t st);
+hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
+                        double tol, hipStream_t st);
+hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
+                         const double *bnorm_src, const int *preconv, double tol, hipStream_t st);
+hipError_t vec_fin_norm(const VecCtx &V, const double *part, double *out, hipStream_t st);
+hipError_t vec_resid(const VecCtx &V, const double *b, const double *q, double *r, double *prr,
+                     hipStream_t st);
+hipError_t vec_scale32(const VecCtx &V, const double *r, const double *nrm, float *r32, hipStream_t st);
+hipError_t vec_correct(const VecCtx &V, const float *d32, const double *nrm, double *x, hipStream_t st);
+
+}  // namespace sipdg

@@ -1,0 +1,126 @@
+// Host construction of the 1-D tables (FP64).
+//
+// GLL nodes: the endpoints and the roots of P'_{n-1}, found by Newton's
+// method from the Chebyshev-Gauss-Lobatto points; weights
+// 2 / (n (n-1) P_{n-1}(x)^2).  Collocation derivative and interpolation use
+// the barycentric form of Lagrange interpolation (Berrut & Trefethen 2004).
+#include "tables.hpp"
+
+#include <cmath>
+#include <cstring>
+
+namespace sipdg {
+
+static void legendre_with_derivs(int p, double x, double *P, double *dP) {
+    P[0] = 1.0;
+    dP[0] = 0.0;
+    if (p >= 1) {
+        P[1] = x;
+        dP[1] = 1.0;
+    }
+    for (int i = 1; i < p; ++i) {
+        P[i + 1] = ((2 * i + 1) * x * P[i] - i * P[i - 1]) / (i + 1);
+        dP[i + 1] = (i + 1) * P[i] + x * dP[i];
+    }
+}
+
+void gll_nodes_weights(int n, double *x, double *w) {
+    const int N = n - 1;  // polynomial degree of P_N
+    double P[NMAX + 2], dP[NMAX + 2];
+    x[0] = -1.0;
+    x[N] = 1.0;
+    for (int j = 1; j < N; ++j) {
+        double t = -std::cos(M_PI * j / N);
+        for (int it = 0; it < 100; ++it) {
+            legendre_with_derivs(N, t, P, dP);
+            // f = P'_N, f' = P''_N = (2 t P'_N - N (N+1) P_N) / (1 - t^2)
+            double f = dP[N];
+            double fp = (2.0 * t * dP[N] - N * (N + 1.0) * P[N]) / (1.0 - t * t);
+            double dt = f / fp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-17) break;
+        }
+        x[j] = t;
+    }
+    for (int j = 0; j < n / 2; ++j) {  // exact symmetry
+        double s = 0.5 * (x[n - 1 - j] - x[j]);
+        x[j] = -s;
+        x[n - 1 - j] = s;
+    }
+    if (n % 2) x[n / 2] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        legendre_with_derivs(N, x[j], P, dP);
+        w[j] = 2.0 / (N * (N + 1.0) * P[N] * P[N]);
+    }
+}
+
+static void bary_weights(int n, const double *x, double *lam) {
+    for (int j = 0; j < n; ++j) {
+        double p = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) p *= (x[j] - x[k]);
+        lam[j] = 1.0 / p;
+    }
+}
+
+void build_tables(double *tab) {
+    std::memset(tab, 0, sizeof(double) * TAB_SIZE);
+    double X[NMAX + 1][NMAX], W[NMAX + 1][NMAX];
+    for (int n = NMIN; n <= NMAX; ++n) {
+        gll_nodes_weights(n, X[n], W[n]);
+        for (int j = 0; j < n; ++j) {
+            tab[tab_off_X(n) + j] = X[n][j];
+            tab[tab_off_W(n) + j] = W[n][j];
+        }
+    }
+    double P[PMAX + 2], dP[PMAX + 2];
+    for (int Pd = 1; Pd <= PMAX; ++Pd) {
+        int n = Pd + 2, np = Pd + 1;
+        for (int q = 0; q < n; ++q) {
+            legendre_with_derivs(Pd, X[n][q], P, dP);
+            for (int i = 0; i < np; ++i) tab[tab_off_B(Pd) + q * np + i] = P[i];
+        }
+    }
+    for (int n = NMIN; n <= NMAX; ++n) {
+        double lam[NMAX];
+        bary_weights(n, X[n], lam);
+        double *D = tab + tab_off_D(n);
+        for (int i = 0; i < n; ++i) {
+            double diag = 0.0;
+            for (int j = 0; j < n; ++j) {
+                if (j == i) continue;
+                double v = (lam[j] / lam[i]) / (X[n][i] - X[n][j]);
+                D[i * n + j] = v;
+                diag -= v;
+            }
+            D[i * n + i] = diag;
+        }
+        for (int m = NMIN; m <= NMAX; ++m) {
+            double *I = tab + tab_off_I(n, m);
+            for (int t = 0; t < m; ++t) {
+                double y = X[m][t];
+                int hit = -1;
+                for (int j = 0; j < n; ++j)
+                    if (y == X[n][j]) hit = j;
+                if (hit >= 0) {
+                    for (int j = 0; j < n; ++j) I[t * n + j] = (j == hit) ? 1.0 : 0.0;
+                    continue;
+                }
+                double den = 0.0;
+                for (int j = 0; j < n; ++j) den += lam[j] / (y - X[n][j]);
+                for (int j = 0; j < n; ++j) I[t * n + j] = (lam[j] / (y - X[n][j])) / den;
+            }
+        }
+    }
+    for (int m = NMIN; m <= NMAX; ++m) {
+        for (int t = 0; t < m; ++t) {
+            legendre_with_derivs(PMAX, X[m][t], P, dP);
+            for (int i = 0; i <= PMAX; ++i) {
+                tab[tab_off_BF(m) + t * (PMAX + 1) + i] = P[i];
+                tab[tab_off_DBF(m) + t * (PMAX + 1) + i] = dP[i];
+            }
+        }
+    }
+}
+
+}  // namespace sipdg
