@@ -1,0 +1,252 @@
+"""Benchmark of the SIPG Helmholtz operator on one MI355X.
+
+Workload: 3-D 32^3 perturbed hex mesh on [0,1]^3, per-element order
+U{3..6} (seeded), lambda = 10, Legendre modes, GLL p+2 points per direction.
+
+A step is one FP64 operator application y = A x (both kernel stages) on
+seeded N(0,1) coefficients already resident in HBM.  value = N_dof / time
+(GDOF/s).  The same line reports the FP32 application, the per-stage kernel
+times, the HBM roofline of one application (algorithmic bytes / measured
+time), the Jacobi-PCG time to a 1e-10 relative residual in FP64 and as FP32
+inner solves inside FP64 iterative refinement (manufactured solution
+sin(pi x) sin(pi y) sin(pi z)), and the CPU oracle timed on a bounded sample
+of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SIPG matvec GDOF/s (FP64 vs FP32+refine) + CG time to 1e-10 residual, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+WORKLOAD = 3
+
+
+def algorithmic_bytes(st, dim, word):
+    """Bytes one application must move: x in, y out, per-point volume
+    factors (G w, d(d+1)/2 values, and w|J|), per trace point the factors
+    (a, and C for each side: 2d+1 interior, d+1 boundary), lambda per element
+    and 32 bytes of connectivity per face."""
+    nvol = st["n_volume_points"]
+    nint = st["n_interior_trace_points"]
+    nbnd = st["n_boundary_trace_points"]
+    nfaces = st["n_interior_faces"] + st["n_boundary_faces"]
+    words = (2 * st["n_dofs"] + nvol * (dim * (dim + 1) // 2 + 1) + nint * (2 * dim + 1)
+             + nbnd * (dim + 1) + st["n_elems"])
+    return word * words + 32 * nfaces
+
+
+def algorithmic_flops(mesh, st):
+    """Sum-factorised flop count of one application (FMA = 2): BwdTrans and
+    IProduct, collocation derivatives and their transposes, pointwise terms,
+    interpolation to and from the trace for the lower-order side of each
+    non-conforming face, and the per-trace-point flux."""
+    import numpy as np
+    d = mesh.dim
+    p = mesh.order.astype(np.int64)
+    n, np_ = p + 2, p + 1
+    if d == 3:
+        bt = 2 * (n * np_ ** 3 + n * n * np_ ** 2 + n ** 3 * np_)
+        der = 2 * d * n ** (d + 1)
+        pw = 20 * n ** 3
+    else:
+        bt = 2 * (n * np_ ** 2 + n * n * np_)
+        der = 2 * d * n ** (d + 1)
+        pw = 10 * n ** 2
+    # trace kernel repeats BwdTrans and derivatives
+    vol = int((2 * bt + 2 * der + pw).sum() + (bt + der).sum())
+    trace = (st["n_interior_trace_points"] * 2 + st["n_boundary_trace_points"]) * (4 * (1 + d) + 12)
+    return vol + trace
+
+
+def source_hash():
+    h = hashlib.sha256()
+    cdir = os.path.join(ROOT, "paper_2504_03573_amd", "csrc")
+    for f in sorted(os.listdir(cdir)):
+        with open(os.path.join(cdir, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_events(fn, n, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def cpu_baseline(mesh, x, budget_s=12.0):
+    """The oracle on a bounded random sample of elements (rows of y = A x)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    om = oracle.prepare(mesh)
+    rng = np.random.default_rng(123)
+    perm = rng.permutation(mesh.n_elems)
+    dofs = (mesh.order.astype(np.int64) + 1) ** mesh.dim
+    k = min(mesh.n_elems, 512)
+    t0 = time.perf_counter()
+    om.apply(x, elems=perm[:k])
+    dt = time.perf_counter() - t0
+    k2 = int(min(mesh.n_elems, max(k, k * budget_s / max(dt, 1e-3))))
+    sel = np.sort(perm[:k2])
+    t0 = time.perf_counter()
+    om.apply(x, elems=sel)
+    dt = time.perf_counter() - t0
+    nd = int(dofs[sel].sum())
+    return {
+        "value": nd / dt / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": f"rows of {k2} of {mesh.n_elems} elements ({nd} of {int(dofs.sum())} DOFs), "
+                  f"{dt:.1f} s, plain FP64 oracle, OpenMP over elements",
+        "seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter scale reference)")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_hex32_p3to6.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2504_03573_amd import SipdgOperator, inspect_mesh
+
+    torch.cuda.set_device(0)
+    mesh = synth.workload(WORKLOAD)
+    st = inspect_mesh(mesh)
+    op = SipdgOperator(mesh)
+    stream = torch.cuda.current_stream()
+    x_np = synth.random_coefficients(mesh, 4000 + WORKLOAD)
+    x = torch.tensor(x_np, device="cuda")
+    y = torch.empty_like(x)
+    x32 = x.float()
+    y32 = torch.empty_like(x32)
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        op.apply(x, out=y)
+        op.apply(x32, out=y32)
+    torch.cuda.synchronize()
+    # timed region: exactly K FP64 applications
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    ms = time_events(lambda: op.apply(x, out=y), args.steps, stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms32 = time_events(lambda: op.apply(x32, out=y32), args.steps, stream)
+    # per-stage times (stage 1: trace kernels, stage 2: flux/volume kernels)
+    op.apply_stage(x, 1)
+    ms_s1 = time_events(lambda: op.apply_stage(x, 1), args.steps, stream)
+    ms_s2 = time_events(lambda: op.apply_stage(x, 2, out=y), args.steps, stream)
+
+    ndof = op.n_dofs
+    b64 = algorithmic_bytes(st, 3, 8)
+    b32 = algorithmic_bytes(st, 3, 4)
+    flops = algorithmic_flops(mesh, st)
+    achieved = b64 / (ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            tr = json.load(open(args.traffic))
+            if tr.get("source_hash") == source_hash():
+                traffic = tr.get("bytes_per_apply")
+        except (OSError, ValueError):
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": ndof / (ms * 1e-3) / 1e9,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3-D hex 32^3 perturbed (+-0.1h) on [0,1]^3, order U{3..6} per element "
+                        "(seed 2003), lambda=10, Legendre modes, GLL p+2, sigma=1",
+            "n_dofs": ndof, "n_elems": op.n_elems,
+            "n_interior_faces": st["n_interior_faces"],
+            "n_nonconforming_faces": st["n_nonconforming_faces"],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "one application: trace kernels + flux/volume kernels (all order groups)",
+            "algorithmic_bytes": b64,
+        },
+        "fp32_apply": {
+            "value": ndof / (ms32 * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms32,
+            "roofline_frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        },
+        "stages_ms": {"trace": ms_s1, "flux_volume": ms_s2},
+        "flops": {"algorithmic_per_apply": flops,
+                  "tflops": flops / (ms * 1e-3) / 1e12,
+                  "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
+        "wall_timed_s": t_wall,
+    }
+    if not args.no_cg:
+        lam = 10.0
+        k = math.pi
+
+        def src(X):
+            return (lam + 3 * k * k) * torch.sin(k * X[:, 0]) * torch.sin(k * X[:, 1]) * torch.sin(k * X[:, 2])
+
+        bvec = op.rhs(src, lambda X: torch.zeros(X.shape[0], dtype=torch.float64, device=X.device))
+        cg = {}
+        for mode in ("f64", "f32_ir"):
+            op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=50, raise_on_fail=False)  # graph capture
+            torch.cuda.synchronize()
+            xs, info = op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=100000, raise_on_fail=False)
+            cg[mode] = {"time_s": info["time_ms"] / 1e3, "iters": info["iters"],
+                        "outer_iters": info["outer_iters"], "rel_resid": info["rel_resid"],
+                        "converged": info["converged"],
+                        "ms_per_iter": info["time_ms"] / max(1, info["iters"])}
+        out["cg"] = cg
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, x_np)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

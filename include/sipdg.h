@@ -85,6 +85,7 @@ typedef struct {
     int64_t n_nonconforming_faces;   /* interior faces with p_L != p_R */
     int64_t orientation_count[8];    /* interior faces per orientation code */
     int64_t n_volume_points, n_trace_points;
+    int64_t n_interior_trace_points, n_boundary_trace_points;
     int64_t elems_per_order[SIPDG_MAX_ORDER + 1];
 } sipdg_mesh_stats;
 
@@ -118,6 +119,18 @@ int sipdg_problem_offsets(sipdg_handle h, int64_t *dof_off, int64_t *elem_off);
  * computed with the FP32 copy of the geometric factors.  x and y must not
  * overlap.  Scratch (the trace buffer) is owned by the handle. */
 int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *stream);
+
+/* One of the two stages of sipdg_apply, async (Sec. 5.1 splits LhsEval the
+ * same way, with the trace exchange between the two parts):
+ *   stage 1: trace values (u and w J_s n.grad u, owner point order) of every
+ *            interior face side into the handle's trace buffer (reads x);
+ *   stage 2: volume terms, shared-trace fluxes (neighbour values from the
+ *            trace buffer, so stage 1 must have run on the same x) and the
+ *            inner products, y written once.
+ * sipdg_apply == stage 1 then stage 2.  For timing and for overlapping the
+ * two parts with other work. */
+int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int stage,
+                      void *stream);
 
 /* xbar = A^T g, async.  The shared-trace SIPG operator is symmetric, so this
  * evaluates the same dataflow as sipdg_apply (Appendix A conditions hold by

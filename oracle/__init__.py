@@ -80,12 +80,17 @@ def _load():
         lib.oracle_sample.argtypes = [P, vp, ctypes.c_int, vp, vp, vp, vp, vp]
         lib.oracle_min_detj.argtypes = [P, vp]
         lib.oracle_face_moments.argtypes = [P, vp, vp]
+        lib.oracle_num_threads.argtypes = []
         for f in (lib.oracle_apply, lib.oracle_diagonal, lib.oracle_points, lib.oracle_rhs,
                   lib.oracle_param_grad, lib.oracle_sample, lib.oracle_min_detj,
-                  lib.oracle_face_moments):
+                  lib.oracle_face_moments, lib.oracle_num_threads):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
 
 
 # ---------------------------------------------------------------- quadrature

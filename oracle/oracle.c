@@ -37,6 +37,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_MAXN 16   /* max quadrature points per direction */
 
@@ -639,4 +642,14 @@ int oracle_face_moments(const omesh *m, double *out_n, double *out_area)
         }
     }
     return 0;
+}
+
+/* Threads the OpenMP loops of this library use. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -53,6 +53,8 @@ class MeshStats(ctypes.Structure):
         ("orientation_count", ctypes.c_int64 * 8),
         ("n_volume_points", ctypes.c_int64),
         ("n_trace_points", ctypes.c_int64),
+        ("n_interior_trace_points", ctypes.c_int64),
+        ("n_boundary_trace_points", ctypes.c_int64),
         ("elems_per_order", ctypes.c_int64 * (MAX_ORDER + 1)),
     ]
 
@@ -100,6 +102,7 @@ SIGNATURES = {
     "sipdg_problem_offsets": (_i, [_vp, _vp, _vp]),
     "sipdg_apply": (_i, [_vp, _vp, _vp, _i, _vp]),
     "sipdg_apply_transpose": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "sipdg_apply_stage": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "sipdg_diagonal": (_i, [_vp, _vp, _vp]),
     "sipdg_param_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "sipdg_set_lambda": (_i, [_vp, _vp, _vp]),

@@ -76,21 +76,25 @@ template OpArgs<double> make_args<double>(const sipdg_ctx *, const Group &, cons
 template OpArgs<float> make_args<float>(const sipdg_ctx *, const Group &, const float *, float *, float *, const int *);
 
 template <class R>
-int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st) {
-    for (const Group &g : c->groups) {
-        OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
-        hipError_t e = launch_op<R>(c->dim, g.P, OP_TRACE, A, g.nfmax, st);
-        if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
+int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages) {
+    if (stages & 1) {
+        for (const Group &g : c->groups) {
+            OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+            hipError_t e = launch_op<R>(c->dim, g.P, OP_TRACE, A, g.nfmax, st);
+            if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
+        }
     }
-    for (const Group &g : c->groups) {
-        OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
-        hipError_t e = launch_op<R>(c->dim, g.P, OP_APPLY, A, g.nfmax, st);
-        if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("apply kernel: ") + hipGetErrorString(e));
+    if (stages & 2) {
+        for (const Group &g : c->groups) {
+            OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+            hipError_t e = launch_op<R>(c->dim, g.P, OP_APPLY, A, g.nfmax, st);
+            if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("apply kernel: ") + hipGetErrorString(e));
+        }
     }
     return SIPDG_OK;
 }
-template int apply_impl<double>(sipdg_ctx *, const double *, double *, double *, const int *, hipStream_t);
-template int apply_impl<float>(sipdg_ctx *, const float *, float *, float *, const int *, hipStream_t);
+template int apply_impl<double>(sipdg_ctx *, const double *, double *, double *, const int *, hipStream_t, int);
+template int apply_impl<float>(sipdg_ctx *, const float *, float *, float *, const int *, hipStream_t, int);
 
 int refresh_diag(sipdg_ctx *c, hipStream_t st) {
     hipError_t e = launch_diag(c->dim, c->ne, c->d_order, c->d_xoff, c->d_voff, c->d_eface, c->d_foff,
@@ -309,6 +313,8 @@ int sipdg_mesh_inspect(const sipdg_mesh_desc *desc, sipdg_mesh_stats *st) {
     for (int o = 0; o < 8; ++o) st->orientation_count[o] = T.orient_count[o];
     st->n_volume_points = T.qoff[T.ne];
     st->n_trace_points = T.n_trace_points;
+    st->n_interior_trace_points = T.n_int_trace_points;
+    st->n_boundary_trace_points = T.n_bnd_trace_points;
     for (int64_t e = 0; e < T.ne; ++e) st->elems_per_order[T.order[e]]++;
     return SIPDG_OK;
 }
@@ -352,6 +358,18 @@ int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *str
         return apply_impl<double>(h, (const double *)x, (double *)y, h->d_tbuf, nullptr, st);
     if (precision == SIPDG_F32)
         return apply_impl<float>(h, (const float *)x, (float *)y, (float *)h->d_tbuf, nullptr, st);
+    return fail(SIPDG_EINVAL, "precision must be SIPDG_F64 or SIPDG_F32");
+}
+
+int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int stage, void *stream) {
+    if (!h || !x || (stage == 2 && !y)) return fail(SIPDG_EINVAL, "null argument");
+    if (stage != 1 && stage != 2) return fail(SIPDG_EINVAL, "stage must be 1 or 2");
+    if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == SIPDG_F64)
+        return apply_impl<double>(h, (const double *)x, (double *)y, h->d_tbuf, nullptr, st, stage);
+    if (precision == SIPDG_F32)
+        return apply_impl<float>(h, (const float *)x, (float *)y, (float *)h->d_tbuf, nullptr, st, stage);
     return fail(SIPDG_EINVAL, "precision must be SIPDG_F64 or SIPDG_F32");
 }
 

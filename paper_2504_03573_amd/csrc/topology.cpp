@@ -257,12 +257,14 @@ int build_topology(int nprob, const sipdg_mesh_desc *descs, Topology &T, std::st
             T.eface[(size_t)r.eL * nlf + r.fL] = {(int)F, 0 | (0 << 2) | (nF << 5)};
             T.eface[(size_t)r.eR * nlf + r.fR] = {(int)F, 1 | (r.orient << 2) | (nF << 5)};
             T.n_interior++;
+            T.n_int_trace_points += npf;
             if (pL != pR) T.n_nonconf++;
             T.orient_count[r.orient]++;
         } else {
             fo += (int64_t)npf * (1 + dim);
             T.eface[(size_t)r.eL * nlf + r.fL] = {(int)F, 2 | (nF << 5)};
             T.n_boundary++;
+            T.n_bnd_trace_points += npf;
         }
         T.n_trace_points += npf;
     }

@@ -16,6 +16,7 @@ struct Topology {
     int64_t ne = 0, ndof = 0, nfaces = 0;
     int64_t vgeo_len = 0, fgeo_len = 0, tbuf_len = 0;
     int64_t n_interior = 0, n_boundary = 0, n_nonconf = 0, n_trace_points = 0;
+    int64_t n_int_trace_points = 0, n_bnd_trace_points = 0;
     int64_t orient_count[8] = {0};
     std::vector<int> order, elem_prob, face_prob;
     std::vector<double> lambda, corners, h, sigma, tau0;

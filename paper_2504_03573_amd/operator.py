@@ -56,6 +56,8 @@ def inspect_mesh(mesh) -> dict:
         "n_nonconforming_faces": st.n_nonconforming_faces,
         "orientation_count": list(st.orientation_count),
         "n_volume_points": st.n_volume_points, "n_trace_points": st.n_trace_points,
+        "n_interior_trace_points": st.n_interior_trace_points,
+        "n_boundary_trace_points": st.n_boundary_trace_points,
         "elems_per_order": list(st.elems_per_order),
     }
 
@@ -130,6 +132,19 @@ class SipdgOperator:
         y = torch.empty_like(x) if out is None else self._vec(out, x.dtype, name="out")
         C.check(self._lib.sipdg_apply(self._h, _ptr(x), _ptr(y), prec, _stream_ptr(stream)))
         return y
+
+    def apply_stage(self, x: torch.Tensor, stage: int, out: torch.Tensor | None = None, stream=None):
+        """Stage 1 (trace values into the handle's buffer) or stage 2 (fluxes,
+        volume terms, inner products into ``out``) of one application."""
+        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        if prec is None:
+            raise TypeError("x must be float64 or float32")
+        self._vec(x, x.dtype, name="x")
+        if stage == 2:
+            out = torch.empty_like(x) if out is None else self._vec(out, x.dtype, name="out")
+        C.check(self._lib.sipdg_apply_stage(self._h, _ptr(x), _ptr(out) if out is not None else None,
+                                            prec, int(stage), _stream_ptr(stream)))
+        return out
 
     def apply_transpose(self, g: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(g.dtype)
