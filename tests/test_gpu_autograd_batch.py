@@ -1,0 +1,226 @@
+"""Autograd Functions (apply and CG solve) and batched handles on the GPU.
+
+Gradients are checked against central finite differences of the same
+quantity (the operator is affine in lambda and sigma, so differences are
+exact up to rounding for the apply) and against the oracle's gradient
+formula; batched results are compared with one handle per problem."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2504_03573_amd as P
+    return P
+
+
+def _mesh():
+    m = synth.workload(5, N=3)
+    return m
+
+
+def test_apply_gradients(P):
+    from paper_2504_03573_amd import autograd as AG
+    print("[apply gradients]", flush=True)
+    m = _mesh()
+    op = P.SipdgOperator(m)
+    rng = np.random.default_rng(3)
+    x = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda", requires_grad=True)
+    wv = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda")
+    lam = torch.tensor(m.lam, device="cuda", requires_grad=True)
+    sig = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    y = AG.apply(op, x, lam, sig)
+    loss = (wv * y).sum()
+    loss.backward()
+    # x: the gradient is A^T w = A w
+    gx_ref = op.apply(wv)
+    assert torch.allclose(x.grad, gx_ref, rtol=1e-13, atol=1e-13 * float(gx_ref.abs().max()))
+    # lambda, sigma: central differences (exact for an affine dependence)
+    with torch.no_grad():
+        for e in (0, 5, 17):
+            h = 1e-3
+            lp = lam.detach().clone(); lp[e] += h
+            lm = lam.detach().clone(); lm[e] -= h
+            fp = float((wv * AG.apply(op, x.detach(), lp, sig.detach())).sum())
+            fm = float((wv * AG.apply(op, x.detach(), lm, sig.detach())).sum())
+            fd = (fp - fm) / (2 * h)
+            assert abs(fd - float(lam.grad[e])) <= 1e-7 * max(1.0, abs(fd)), (e, fd, float(lam.grad[e]))
+        h = 1e-4
+        fp = float((wv * AG.apply(op, x.detach(), lam.detach(), sig.detach() + h)).sum())
+        fm = float((wv * AG.apply(op, x.detach(), lam.detach(), sig.detach() - h)).sum())
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - float(sig.grad)) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_apply_gradients_match_oracle(P):
+    import oracle
+    oracle.build(force=False)
+    from paper_2504_03573_amd import autograd as AG
+    m = _mesh()
+    op = P.SipdgOperator(m)
+    om = oracle.prepare(m)
+    rng = np.random.default_rng(4)
+    xa = rng.standard_normal(op.n_dofs)
+    wa = rng.standard_normal(op.n_dofs)
+    x = torch.tensor(xa, device="cuda")
+    lam = torch.tensor(m.lam, device="cuda", requires_grad=True)
+    sig = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    (torch.tensor(wa, device="cuda") * AG.apply(op, x, lam, sig)).sum().backward()
+    dl, ds = om.param_grad(wa, xa)
+    assert np.linalg.norm(lam.grad.cpu().numpy() - dl) <= 1e-12 * np.linalg.norm(dl)
+    assert abs(float(sig.grad) - ds) <= 1e-12 * abs(ds)
+
+
+def test_solve_gradients_fd(P):
+    from paper_2504_03573_amd import autograd as AG
+    print("[solve gradients]", flush=True)
+    m = _mesh()
+    op = P.SipdgOperator(m)
+    rng = np.random.default_rng(5)
+    b = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda", requires_grad=True)
+    target = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda") * 1e-3
+    lam = torch.tensor(m.lam, device="cuda", requires_grad=True)
+    sig = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def loss_of(lam_, sig_, b_):
+        u = AG.solve(op, b_, lam_, sig_, tol=1e-13)
+        return ((u - target) ** 2).sum()
+
+    loss = loss_of(lam, sig, b)
+    loss.backward()
+    with torch.no_grad():
+        for e in (1, 9):
+            h = 1e-4 * float(lam[e])
+            lp = lam.detach().clone(); lp[e] += h
+            lm = lam.detach().clone(); lm[e] -= h
+            fd = (float(loss_of(lp, sig.detach(), b.detach())) - float(loss_of(lm, sig.detach(), b.detach()))) / (2 * h)
+            assert abs(fd - float(lam.grad[e])) <= 1e-5 * abs(fd) + 1e-14, (e, fd, float(lam.grad[e]))
+        h = 1e-5
+        fd = (float(loss_of(lam.detach(), sig.detach() + h, b.detach()))
+              - float(loss_of(lam.detach(), sig.detach() - h, b.detach()))) / (2 * h)
+        assert abs(fd - float(sig.grad)) <= 1e-5 * abs(fd) + 1e-14
+        # b: directional derivative
+        d = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda")
+        h = 1e-3
+        fd = (float(loss_of(lam.detach(), sig.detach(), b.detach() + h * d))
+              - float(loss_of(lam.detach(), sig.detach(), b.detach() - h * d))) / (2 * h)
+        assert abs(fd - float((b.grad * d).sum())) <= 1e-6 * abs(fd) + 1e-14
+
+
+def test_lambda_recovery(P):
+    """Recover a seeded per-element lambda field from an observed solution by
+    gradient descent on log(lambda) through the solve."""
+    from paper_2504_03573_amd import autograd as AG
+    print("[lambda recovery]", flush=True)
+    m = _mesh()
+    op = P.SipdgOperator(m)
+    lam_true = torch.tensor(m.lam, device="cuda")
+    sig = torch.tensor(1.0, dtype=torch.float64, device="cuda")
+    k = np.pi
+    b = op.rhs(lambda X: (12.0 + 3 * k * k) * torch.sin(k * X[:, 0]) * torch.sin(k * X[:, 1]) * torch.sin(k * X[:, 2]),
+               lambda X: torch.zeros(X.shape[0], dtype=torch.float64, device=X.device))
+    with torch.no_grad():
+        u_obs = AG.solve(op, b, lam_true, sig)
+    theta = torch.full((op.n_elems,), float(np.log(3.0)), dtype=torch.float64, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([theta], lr=0.08)
+    losses = []
+    scale = float((u_obs ** 2).sum())
+    for it in range(80):
+        opt.zero_grad()
+        u = AG.solve(op, b, torch.exp(theta), sig)
+        loss = ((u - u_obs) ** 2).sum() / scale
+        loss.backward()
+        opt.step()
+        losses.append(loss.item())
+    err0 = float((np.log(3.0) - torch.log(lam_true)).abs().mean())
+    err1 = float((theta.detach() - torch.log(lam_true)).abs().mean())
+    print(f"loss {losses[0]:.3e} -> {losses[-1]:.3e}; mean |log lam err| {err0:.3f} -> {err1:.3f}")
+    assert losses[-1] < 1e-3 * losses[0]
+    assert err1 < 0.5 * err0
+
+
+def _batch_meshes():
+    ms = []
+    rng = np.random.default_rng(9)
+    for i, (n, p) in enumerate([(2, 2), (3, 4), (2, 7), (1, 3)]):
+        mm = synth.structured_mesh(3, n, 0.1, seed=500 + i, order=p, lam=float(10 ** rng.uniform(-1, 2)))
+        ms.append(mm)
+    ms.append(synth.small_mesh(3, 2, ("random", 2, 6), seed=77, rotate=True, lam=0.7))
+    return ms
+
+
+def test_batch_apply_equals_single(P):
+    print("[batch apply]", flush=True)
+    ms = _batch_meshes()
+    bop = P.SipdgOperator.batch(ms)
+    singles = [P.SipdgOperator(mm) for mm in ms]
+    assert bop.n_problems == len(ms)
+    rng = np.random.default_rng(1)
+    x = torch.tensor(rng.standard_normal(bop.n_dofs), device="cuda")
+    y = bop.apply(x)
+    off = bop.problem_dof_offsets
+    for i, op in enumerate(singles):
+        xi = x[off[i]:off[i + 1]].contiguous()
+        yi = op.apply(xi)
+        assert torch.equal(yi, y[off[i]:off[i + 1]]), i
+    y32 = bop.apply(x.float())
+    for i, op in enumerate(singles):
+        assert torch.equal(op.apply(x[off[i]:off[i + 1]].float().contiguous()), y32[off[i]:off[i + 1]])
+
+
+def test_batch_cg_per_problem(P):
+    print("[batch cg]", flush=True)
+    ms = _batch_meshes()
+    bop = P.SipdgOperator.batch(ms)
+    rng = np.random.default_rng(2)
+    xt = torch.tensor(rng.standard_normal(bop.n_dofs), device="cuda")
+    b = bop.apply(xt)
+    off = bop.problem_dof_offsets
+    for mode in ("f64", "f32_ir"):
+        xs, info = bop.cg_solve(b, tol=1e-10, mode=mode)
+        assert info["converged"] and info["rel_resid"] <= 1e-10, info
+        r = b - bop.apply(xs)
+        for i in range(len(ms)):
+            ri = float(r[off[i]:off[i + 1]].norm() / b[off[i]:off[i + 1]].norm())
+            assert ri <= 1e-10, (mode, i, ri)
+    # per-problem sigma gradients equal single-problem ones
+    a = torch.tensor(rng.standard_normal(bop.n_dofs), device="cuda")
+    dl, ds = bop.param_grad(a, xt)
+    for i, mm in enumerate(ms):
+        op = P.SipdgOperator(mm)
+        dli, dsi = op.param_grad(a[off[i]:off[i + 1]].contiguous(), xt[off[i]:off[i + 1]].contiguous())
+        eo = bop.problem_elem_offsets
+        assert torch.allclose(dl[eo[i]:eo[i + 1]], dli, rtol=1e-14, atol=0)
+        assert abs(float(ds[i]) - float(dsi[0])) <= 1e-13 * abs(float(dsi[0]))
+
+
+def test_cg_checkpoint_resume_and_failures(P):
+    print("[cg checkpoint / failure paths]", flush=True)
+    m = synth.workload(5, N=3)
+    op = P.SipdgOperator(m)
+    rng = np.random.default_rng(8)
+    b = op.apply(torch.tensor(rng.standard_normal(op.n_dofs), device="cuda"))
+    snaps = []
+    x, info = op.cg_solve(b, tol=1e-10, graph_k=5, checkpoint=lambda xs, rs, it: snaps.append((it, xs.clone())),
+                          checkpoint_every=20)
+    assert snaps and info["converged"]
+    it0, x0 = snaps[len(snaps) // 2]
+    x2, info2 = op.cg_solve(b, tol=1e-10, x0=x0)
+    assert info2["converged"] and info2["iters"] < info["iters"]
+    # maxit exhausted
+    _, info3 = op.cg_solve(b, tol=1e-10, maxit=3, raise_on_fail=False)
+    assert info3["status"] == -5 and not info3["converged"]
+    # indefinite operator (negative lambda) reports a breakdown
+    op.set_lambda(torch.full((op.n_elems,), -1e6, dtype=torch.float64, device="cuda"))
+    _, info4 = op.cg_solve(b, tol=1e-10, raise_on_fail=False, precond=False)
+    assert info4["status"] == -6
