@@ -146,6 +146,7 @@ def main():
     mesh = synth.workload(WORKLOAD)
     st = inspect_mesh(mesh)
     op = SipdgOperator(mesh)
+    tuned = op.autotune(20)
     stream = torch.cuda.current_stream()
     x_np = synth.random_coefficients(mesh, 4000 + WORKLOAD)
     x = torch.tensor(x_np, device="cuda")
@@ -212,7 +213,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "one application: trace kernels + flux/volume kernels (all order groups)",
+            "kernel": "one application, all order groups (kernel structure: %s)" % op.variant,
             "algorithmic_bytes": b64,
         },
         "fp32_apply": {
@@ -220,6 +221,8 @@ def main():
             "roofline_frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "stages_ms": {"trace": ms_s1, "flux_volume": ms_s2},
+        "variant": op.variant,
+        "autotune_ms": tuned,
         "flops": {"algorithmic_per_apply": flops,
                   "tflops": flops / (ms * 1e-3) / 1e12,
                   "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},

@@ -132,6 +132,28 @@ int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *str
 int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int stage,
                       void *stream);
 
+/* Kernel structure of sipdg_apply (same results to rounding):
+ *   GATHER:    trace values gathered from the element's quadrature points and
+ *              interpolated to the trace (Sec. 3.2 GathrInterp), lifted by the
+ *              transposed interpolation; two launches per order group; any
+ *              dimension and order.
+ *   TWO_STAGE: trace values evaluated directly from the coefficients
+ *              (TracePhysEval) and lifted by TraceIProduct, one wavefront per
+ *              element; trace kernel then apply kernel.  3-D, orders <= 6.
+ *              Default when allowed (GATHER otherwise).
+ *   FUSED:     as TWO_STAGE, but each element evaluates its neighbours'
+ *              traces from their coefficients, so one launch per order group
+ *              and no trace buffer.  3-D, orders <= 6. */
+#define SIPDG_VARIANT_GATHER    0
+#define SIPDG_VARIANT_TWO_STAGE 1
+#define SIPDG_VARIANT_FUSED     2
+int sipdg_set_variant(sipdg_handle h, int variant);   /* EINVAL if not allowed */
+int sipdg_get_variant(sipdg_handle h, int *variant);
+/* Time one FP64 application with every allowed variant (reps each, HIP
+ * events on the stream) and keep the fastest.  ms_out (host, [3], may be
+ * NULL) receives the times (0 for variants not allowed).  Synchronous. */
+int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream);
+
 /* xbar = A^T g, async.  The shared-trace SIPG operator is symmetric, so this
  * evaluates the same dataflow as sipdg_apply (Appendix A conditions hold by
  * construction). */

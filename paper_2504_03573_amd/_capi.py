@@ -25,6 +25,7 @@ SIPDG_F32 = 1
 SIPDG_CG_F64 = 0
 SIPDG_CG_F32_IR = 1
 MAX_ORDER = 8
+VARIANTS = {"gather": 0, "two_stage": 1, "fused": 2}
 
 c_int64_p = ctypes.POINTER(ctypes.c_int64)
 
@@ -112,6 +113,9 @@ SIGNATURES = {
     "sipdg_load_vector": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "sipdg_cg_default_opts": (None, [ctypes.POINTER(CgOpts)]),
     "sipdg_cg_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgInfo), _vp]),
+    "sipdg_set_variant": (_i, [_vp, _i]),
+    "sipdg_get_variant": (_i, [_vp, ctypes.POINTER(_i)]),
+    "sipdg_autotune": (_i, [_vp, _i, _vp, _vp]),
     "sipdg_last_error": (ctypes.c_char_p, []),
 }
 

@@ -9,6 +9,8 @@
 #include "api_common.hpp"
 #include "sipdg.h"
 #include "topology.hpp"
+#include "fast3d.hpp"
+#include <cstdlib>
 
 using namespace sipdg;
 
@@ -76,7 +78,64 @@ template OpArgs<double> make_args<double>(const sipdg_ctx *, const Group &, cons
 template OpArgs<float> make_args<float>(const sipdg_ctx *, const Group &, const float *, float *, float *, const int *);
 
 template <class R>
+hipError_t launch_fast3d(int P, int kind, const f3::Args3 &A, const f3::Data3<R> &D, hipStream_t st);
+
+template <class R>
+static void fast_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *tbuf, const int *skip,
+                      bool fused, f3::Args3 &A, f3::Data3<R> &D) {
+    A.elems = g.d_elems;
+    A.count = g.count;
+    A.region = 0;
+    A.xoff = c->d_xoff;
+    A.voff = c->d_voff;
+    A.eface = c->d_eface;
+    A.faces = c->d_faces;
+    A.order = c->d_order;
+    A.foff = c->d_foff;
+    A.toff = c->d_toff;
+    A.skip = skip;
+    if constexpr (sizeof(R) == 8) {
+        D.vgeo = (const R *)c->d_vgeo64;
+        D.fgeo = (const R *)c->d_fgeo64;
+        D.lam = (const R *)c->d_lam64;
+        D.tau = (const R *)c->d_tau64;
+        D.tab = (const R *)c->d_tab64;
+    } else {
+        D.vgeo = (const R *)c->d_vgeo32;
+        D.fgeo = (const R *)c->d_fgeo32;
+        D.lam = (const R *)c->d_lam32;
+        D.tau = (const R *)c->d_tau32;
+        D.tab = (const R *)c->d_tab32;
+    }
+    D.x = x;
+    D.y = y;
+    D.tbuf = tbuf;
+}
+
+template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages) {
+    if (c->variant != SIPDG_VARIANT_GATHER) {
+        const bool fused = c->variant == SIPDG_VARIANT_FUSED;
+        if ((stages & 1) && !fused) {
+            for (const Group &g : c->groups) {
+                f3::Args3 A;
+                f3::Data3<R> D;
+                fast_args<R>(c, g, x, y, tbuf, skip, false, A, D);
+                hipError_t e = launch_fast3d<R>(g.P, 0, A, D, st);
+                if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
+            }
+        }
+        if (stages & 2) {
+            for (const Group &g : c->groups) {
+                f3::Args3 A;
+                f3::Data3<R> D;
+                fast_args<R>(c, g, x, y, tbuf, skip, fused, A, D);
+                hipError_t e = launch_fast3d<R>(g.P, fused ? 2 : 1, A, D, st);
+                if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("apply kernel: ") + hipGetErrorString(e));
+            }
+        }
+        return SIPDG_OK;
+    }
     if (stages & 1) {
         for (const Group &g : c->groups) {
             OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
@@ -268,6 +327,19 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
                                           " bytes of LDS per block, device allows " + std::to_string(limit));
         }
     }
+    {
+        int pmax = 0;
+        for (int o : T.order) pmax = std::max(pmax, o);
+        c->fast_ok = T.dim == 3 && pmax <= 6;
+        c->variant = c->fast_ok ? SIPDG_VARIANT_TWO_STAGE : SIPDG_VARIANT_GATHER;
+        const char *env = std::getenv("SIPDG_VARIANT");
+        if (env && c->fast_ok) {
+            std::string v(env);
+            if (v == "gather") c->variant = SIPDG_VARIANT_GATHER;
+            else if (v == "two_stage") c->variant = SIPDG_VARIANT_TWO_STAGE;
+            else if (v == "fused") c->variant = SIPDG_VARIANT_FUSED;
+        }
+    }
     TRY(dalloc(&c->d_diag64, T.ndof));
     TRY(dalloc(&c->d_dinv64, T.ndof));
     TRY(dalloc(&c->d_dinv32, T.ndof));
@@ -456,6 +528,66 @@ int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *d
     HIPCHK(launch_segsum(h->nprob, h->d_prob_face_off, h->d_face_tmp, dsig, 0, st));
     HIPCHK(launch_segsum(h->nprob, h->d_prob_elem_off, h->d_elem_tmp, dsig, 1, st));
     return SIPDG_OK;
+}
+
+int sipdg_set_variant(sipdg_handle h, int variant) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (variant == SIPDG_VARIANT_GATHER) {
+        h->variant = variant;
+        return SIPDG_OK;
+    }
+    if (variant != SIPDG_VARIANT_TWO_STAGE && variant != SIPDG_VARIANT_FUSED)
+        return fail(SIPDG_EINVAL, "unknown variant");
+    if (!h->fast_ok) return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
+    h->variant = variant;
+    return SIPDG_OK;
+}
+
+int sipdg_get_variant(sipdg_handle h, int *variant) {
+    if (!h || !variant) return fail(SIPDG_EINVAL, "null argument");
+    *variant = h->variant;
+    return SIPDG_OK;
+}
+
+int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (reps <= 0) reps = 20;
+    hipStream_t st = (hipStream_t)stream;
+    double *x = nullptr, *y = nullptr;
+    HIPCHK(hipMalloc((void **)&x, sizeof(double) * std::max<int64_t>(1, h->ndof)));
+    HIPCHK(hipMalloc((void **)&y, sizeof(double) * std::max<int64_t>(1, h->ndof)));
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * h->ndof, st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int keep = h->variant;
+    double best = 1e300;
+    int best_v = keep;
+    int rc = SIPDG_OK;
+    for (int v = 0; v < 3 && rc == SIPDG_OK; ++v) {
+        if (ms_out) ms_out[v] = 0.0;
+        if (v != SIPDG_VARIANT_GATHER && !h->fast_ok) continue;
+        h->variant = v;
+        for (int i = 0; i < 3 && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SIPDG_EHIP, "event record");
+        for (int i = 0; i < reps && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = fail(SIPDG_EHIP, "event sync");
+        float ms = 0.f;
+        if (rc == SIPDG_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+            const double t = ms / reps;
+            if (ms_out) ms_out[v] = t;
+            if (t < best) {
+                best = t;
+                best_v = v;
+            }
+        }
+    }
+    h->variant = rc == SIPDG_OK ? best_v : keep;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    return rc;
 }
 
 const char *sipdg_last_error(void) { return g_last_error.c_str(); }

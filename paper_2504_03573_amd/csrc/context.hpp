@@ -102,4 +102,6 @@ struct sipdg_ctx {
     float *d_dinv32 = nullptr;
     std::vector<sipdg::Group> groups;
     sipdg::CgWork *cg = nullptr;
+    int variant = 0;        // SIPDG_VARIANT_*
+    bool fast_ok = false;   // 3-D with every order <= 6
 };

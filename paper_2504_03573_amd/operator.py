@@ -155,6 +155,22 @@ class SipdgOperator:
         C.check(self._lib.sipdg_apply_transpose(self._h, _ptr(g), _ptr(y), prec, _stream_ptr(stream)))
         return y
 
+    @property
+    def variant(self) -> str:
+        v = ctypes.c_int()
+        C.check(self._lib.sipdg_get_variant(self._h, ctypes.byref(v)))
+        return {b: a for a, b in C.VARIANTS.items()}[v.value]
+
+    @variant.setter
+    def variant(self, name: str):
+        C.check(self._lib.sipdg_set_variant(self._h, C.VARIANTS[name]))
+
+    def autotune(self, reps: int = 20, stream=None) -> dict:
+        """Time every allowed kernel structure and keep the fastest."""
+        ms = (ctypes.c_double * 3)()
+        C.check(self._lib.sipdg_autotune(self._h, int(reps), ms, _stream_ptr(stream)))
+        return {name: ms[i] for name, i in C.VARIANTS.items() if ms[i] > 0}
+
     def diagonal(self, stream=None) -> torch.Tensor:
         d = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         C.check(self._lib.sipdg_diagonal(self._h, _ptr(d), _stream_ptr(stream)))

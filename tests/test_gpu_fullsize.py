@@ -54,8 +54,10 @@ def test_workload_sampled_rows(env, k):
     elems = np.sort(rng.choice(m.n_elems, size=300, replace=False))
     y_ref = om.apply(x, elems=elems)
     rows = _rows(om, om.dof_off, elems)
-    y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
-    assert np.linalg.norm(y[rows] - y_ref[rows]) <= 1e-12 * np.linalg.norm(y_ref[rows])
+    for v in (["gather", "two_stage", "fused"] if op.variant != "gather" else ["gather"]):
+        op.variant = v
+        y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(y[rows] - y_ref[rows]) <= 1e-12 * np.linalg.norm(y_ref[rows]), v
     y32 = op.apply(torch.tensor(x, device="cuda", dtype=torch.float32)).double().cpu().numpy()
     assert np.linalg.norm(y32[rows] - y_ref[rows]) <= 1e-5 * np.linalg.norm(y_ref[rows])
     # properties at full size: symmetry and determinism
