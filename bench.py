@@ -186,7 +186,7 @@ def main():
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
-            if tr.get("source_hash") == source_hash():
+            if tr.get("source_hash") == source_hash() and tr.get("variant") == op.variant:
                 traffic = tr.get("bytes_per_apply")
         except (OSError, ValueError):
             traffic = None

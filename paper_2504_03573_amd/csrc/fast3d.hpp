@@ -188,7 +188,8 @@ template <class R>
 __device__ __forceinline__ void load_tables(const Side sd[2], const R *__restrict__ tab, int npx, R *TB) {
     for (int i = lane_id(); i < 4 * G8; i += W) {
         const int s = i >> 7, c = (i >> 6) & 1, t = (i >> 3) & 7, m = i & 7;
-        const int nf = sd[s].nf;
+        // s depends on the lane: select, so that sd stays in registers
+        const int nf = s ? sd[1].nf : sd[0].nf;
         R v = R(0);
         if (t < nf && m < npx) v = tab[(c ? tab_off_DBF(nf) : tab_off_BF(nf)) + t * S9 + m];
         TB[i] = v;
@@ -336,9 +337,11 @@ __device__ __forceinline__ void nbr_eval(const Args3 &A, const Data3<R> &D, int 
     // tables padded to the neighbours' mode counts
     for (int i = lane_id(); i < 4 * G8; i += W) {
         const int s = i >> 7, c = (i >> 6) & 1, t = (i >> 3) & 7, m = i & 7;
-        const int nf = sd[s].nf;
+        const int nf = s ? sd[1].nf : sd[0].nf;
+        const bool as = s ? act[1] : act[0];
+        const int nps = s ? npn[1] : npn[0];
         R v = R(0);
-        if (act[s] && t < nf && m < npn[s]) v = D.tab[(c ? tab_off_DBF(nf) : tab_off_BF(nf)) + t * S9 + m];
+        if (as && t < nf && m < nps) v = D.tab[(c ? tab_off_DBF(nf) : tab_off_BF(nf)) + t * S9 + m];
         TB[i] = v;
     }
     __syncthreads();
