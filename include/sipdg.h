@@ -140,17 +140,31 @@ int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int
  *   TWO_STAGE: trace values evaluated directly from the coefficients
  *              (TracePhysEval) and lifted by TraceIProduct, one wavefront per
  *              element; trace kernel then apply kernel.  3-D, orders <= 6.
- *              Default when allowed (GATHER otherwise).
  *   FUSED:     as TWO_STAGE, but each element evaluates its neighbours'
  *              traces from their coefficients, so one launch per order group
- *              and no trace buffer.  3-D, orders <= 6. */
-#define SIPDG_VARIANT_GATHER    0
-#define SIPDG_VARIANT_TWO_STAGE 1
-#define SIPDG_VARIANT_FUSED     2
+ *              and no trace buffer.  3-D, orders <= 6.
+ *   GATHER_FOLD: one wavefront per element with the volume in registers;
+ *              the element's own face values are gathered from its GLL face
+ *              points (interpolated with I when the trace is finer) and the
+ *              lifted flux is added to the volume's pointwise terms so that
+ *              one IProduct lifts faces and volume (Sec. 3.2 GathrInterp;
+ *              Sec. 3.3).  A trace kernel stores every interior face side's
+ *              (u, g), then the apply kernel reads the neighbour's.  3-D,
+ *              orders <= 6.  Default when allowed (GATHER otherwise).
+ *   GATHER_FOLD_FUSED: as GATHER_FOLD, but the neighbour's traces are
+ *              evaluated from its coefficients (TracePhysEval): one launch
+ *              per order group, no trace buffer.  3-D, orders <= 6. */
+#define SIPDG_VARIANT_GATHER            0
+#define SIPDG_VARIANT_TWO_STAGE         1
+#define SIPDG_VARIANT_FUSED             2
+#define SIPDG_VARIANT_GATHER_FOLD       3
+#define SIPDG_VARIANT_GATHER_FOLD_FUSED 4
+#define SIPDG_NUM_VARIANTS              5
 int sipdg_set_variant(sipdg_handle h, int variant);   /* EINVAL if not allowed */
 int sipdg_get_variant(sipdg_handle h, int *variant);
 /* Time one FP64 application with every allowed variant (reps each, HIP
- * events on the stream) and keep the fastest.  ms_out (host, [3], may be
+ * events on the stream) and keep the fastest.  ms_out (host,
+ * [SIPDG_NUM_VARIANTS], may be
  * NULL) receives the times (0 for variants not allowed).  Synchronous. */
 int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream);
 

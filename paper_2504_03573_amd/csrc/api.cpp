@@ -10,6 +10,7 @@
 #include "sipdg.h"
 #include "topology.hpp"
 #include "fast3d.hpp"
+#include "gfold3d.hpp"
 #include <cstdlib>
 
 using namespace sipdg;
@@ -113,7 +114,29 @@ static void fast_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *t
 }
 
 template <class R>
+hipError_t launch_gfold3d(int P, int mode, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+
+template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages) {
+    if (c->variant == SIPDG_VARIANT_GATHER_FOLD || c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED) {
+        const bool fused = c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED;
+        for (int stage = 1; stage <= 2; ++stage) {
+            if (!(stages & stage) || (fused && stage == 1)) continue;
+            const int mode = stage == 1 ? 0 : (fused ? 2 : 1);
+            for (const Group &g : c->groups) {
+                f3::Args3 A3;
+                f3::Data3<R> D3;
+                fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
+                g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff, A3.skip};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                hipError_t e = launch_gfold3d<R>(g.P, mode, A, D, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
+                                                hipGetErrorString(e));
+            }
+        }
+        return SIPDG_OK;
+    }
     if (c->variant != SIPDG_VARIANT_GATHER) {
         const bool fused = c->variant == SIPDG_VARIANT_FUSED;
         if ((stages & 1) && !fused) {
@@ -331,13 +354,15 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         int pmax = 0;
         for (int o : T.order) pmax = std::max(pmax, o);
         c->fast_ok = T.dim == 3 && pmax <= 6;
-        c->variant = c->fast_ok ? SIPDG_VARIANT_TWO_STAGE : SIPDG_VARIANT_GATHER;
+        c->variant = c->fast_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
         const char *env = std::getenv("SIPDG_VARIANT");
         if (env && c->fast_ok) {
             std::string v(env);
             if (v == "gather") c->variant = SIPDG_VARIANT_GATHER;
             else if (v == "two_stage") c->variant = SIPDG_VARIANT_TWO_STAGE;
             else if (v == "fused") c->variant = SIPDG_VARIANT_FUSED;
+            else if (v == "gather_fold") c->variant = SIPDG_VARIANT_GATHER_FOLD;
+            else if (v == "gather_fold_fused") c->variant = SIPDG_VARIANT_GATHER_FOLD_FUSED;
         }
     }
     TRY(dalloc(&c->d_diag64, T.ndof));
@@ -536,7 +561,7 @@ int sipdg_set_variant(sipdg_handle h, int variant) {
         h->variant = variant;
         return SIPDG_OK;
     }
-    if (variant != SIPDG_VARIANT_TWO_STAGE && variant != SIPDG_VARIANT_FUSED)
+    if (variant < 0 || variant >= SIPDG_NUM_VARIANTS)
         return fail(SIPDG_EINVAL, "unknown variant");
     if (!h->fast_ok) return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
     h->variant = variant;
@@ -564,7 +589,7 @@ int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
     double best = 1e300;
     int best_v = keep;
     int rc = SIPDG_OK;
-    for (int v = 0; v < 3 && rc == SIPDG_OK; ++v) {
+    for (int v = 0; v < SIPDG_NUM_VARIANTS && rc == SIPDG_OK; ++v) {
         if (ms_out) ms_out[v] = 0.0;
         if (v != SIPDG_VARIANT_GATHER && !h->fast_ok) continue;
         h->variant = v;

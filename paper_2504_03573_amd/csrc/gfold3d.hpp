@@ -1,0 +1,818 @@
+// Gather-fold hexahedron kernel, orders 1..6 (n = p+2 <= 8 GLL points per
+// direction), one 64-lane wavefront per element, one launch per order group.
+//
+// Volume terms (Xia & Moxey, Sec. 3.1 basic operators): lane (q0, q1) keeps
+// the xi_2 column of its n points in registers ("column layout").  BwdTrans,
+// the collocation derivative and their transposes are line contractions
+// whose 1-D table entries are wave-uniform, so they come through the scalar
+// cache; LDS is used only to move lines between the three layouts
+//   column  lane (q0, q1) holds (q0, q1, .)
+//   line-0  lane (q1, q2) holds (., q1, q2)
+//   line-1  lane (q0, q2) holds (q0, ., q2)
+// through two padded point arrays whose strides (9 along q1, 72/56/40/24 along
+// q2) keep the three access patterns on distinct LDS banks.
+//
+// Faces (Sec. 3.2 GathrInterp, Sec. 3.3 shared trace space): GLL points
+// include the element's faces, so u and grad_xi u at an element's own face
+// points fall out of the volume evaluation: a column's ends for the faces
+// normal to xi_2, a line-0 or line-1 lane's ends for the faces normal to xi_0
+// and xi_1.  In every face phase lane (t1, t2) holds trace point (t1, t2) in
+// the element's own face coordinates.  When the shared trace is finer than the
+// element (n_F > n), the four fields are interpolated to the trace with the
+// Lagrange matrix I (n_F x n) and the flux is brought back with I^T, which is
+// exact because everything interpolated is a polynomial of degree <= p on the
+// face (the transposed evaluation of Sec. 3.3, TraceIProduct).  The
+// neighbour's u and grad_xi u at the same trace points are evaluated from its
+// coefficients (TracePhysEval: a reduction along its face normal with
+// P_i(+-1), P'_i(+-1) and two contractions with the Legendre tables at the
+// trace's GLL points), directly at the points given by the orientation map.
+// The flux of eq. IP is formed at every trace point and its lift -- a value
+// for the phi test term and a vector for the grad phi test term -- is added to
+// the volume's pointwise terms at the face points, so the inner product with
+// the basis (IProduct) lifts faces and volume at once and y is written once.
+#pragma once
+
+#include "context.hpp"
+#include "launch.hpp"
+
+namespace sipdg {
+namespace g3 {
+
+constexpr int W = 64;           // lanes per element
+constexpr int S9 = PMAX + 1;    // row stride of the BF/DBF tables
+
+template <int P>
+struct Sz {
+    static constexpr int N = P + 2, NP = P + 1;
+    static constexpr int NPTS = N * N * N;
+    static constexpr int S1 = 9;
+    static constexpr int S2 = N >= 7 ? 72 : (N >= 5 ? 56 : (N == 4 ? 40 : 24));
+    static constexpr int ARR = S2 * N;     // one padded point array
+    static constexpr int SCR = 1024;       // face scratch, aliases the point arrays
+    static constexpr int TOTAL = 2 * ARR > SCR ? 2 * ARR : SCR;
+};
+
+// face scratch (R units from the block's LDS base):
+//   FB [2 sides][4 fields][64]   lifted flux of the faces normal to xi_0 / xi_1
+//   NU [2][64], NW [3][64]       neighbour trace evaluation
+//   IS [4][64], IT [4][64]       interpolation to / from a finer trace (aliases NU, NW)
+constexpr int FB_OFF = 0, NU_OFF = 512, NW_OFF = 640, IS_OFF = 512, IT_OFF = 768;
+
+struct Args {
+    const int *elems;
+    int count;
+    const int64_t *xoff;
+    const int64_t *voff;
+    const FaceRef *eface;
+    const FaceTopo *faces;
+    const int *order;
+    const int64_t *foff;
+    const int64_t *toff;
+    const int *skip;
+};
+
+template <class R>
+struct Data {
+    const R *__restrict__ vgeo;
+    const R *__restrict__ fgeo;
+    const R *__restrict__ lam;
+    const R *__restrict__ tau;
+    const R *__restrict__ tab;
+    const R *__restrict__ x;
+    R *__restrict__ y;
+    R *__restrict__ tbuf;
+};
+
+// Tables are read through the constant address space: the compiler may then
+// assume no store of the kernel writes them and reads wave-uniform entries
+// with scalar loads (a __restrict__ on a struct member does not tell it that).
+template <class R>
+using ctab = const __attribute__((address_space(4))) R *;
+template <class R>
+__device__ __forceinline__ ctab<R> as_const(const R *p) {
+    return (ctab<R>)p;
+}
+
+template <int P>
+__device__ __forceinline__ int pa(int i0, int i1, int i2) {
+    return i0 + Sz<P>::S1 * i1 + Sz<P>::S2 * i2;
+}
+
+// face coordinate directions of the face normal to k (increasing order)
+__device__ __forceinline__ int dir_a(int k) { return k == 0 ? 1 : 0; }
+__device__ __forceinline__ int dir_b(int k) { return k == 2 ? 1 : 2; }
+
+// P_i(s) and P'_i(s) at s = -1 (side 0) and +1 (side 1)
+template <class R>
+__device__ __forceinline__ R end_val(int i, int s) { return (s || !(i & 1)) ? R(1) : R(-1); }
+template <class R>
+__device__ __forceinline__ R end_der(int i, int s) {
+    const R v = R(0.5) * R(i) * R(i + 1);
+    return (s || (i & 1)) ? v : -v;
+}
+
+// mode with face indices (ia, ib) and normal index ik on the face normal to k
+__device__ __forceinline__ int mode_rt(int np, int k, int ia, int ib, int ik) {
+    if (k == 0) return ik + np * (ia + np * ib);
+    if (k == 1) return ia + np * (ik + np * ib);
+    return ia + np * (ib + np * ik);
+}
+
+// canonical (owner) trace index -> face coordinates of a side with
+// orientation code o (inverse of canon_index)
+__device__ __forceinline__ void canon_inverse(int o, int nf, int qc, int &r1, int &r2) {
+    const int c1 = qc % nf, c2 = qc / nf;
+    const int a1 = (o & 4) ? c2 : c1, a2 = (o & 4) ? c1 : c2;
+    r1 = (o & 1) ? nf - 1 - a1 : a1;
+    r2 = (o & 2) ? nf - 1 - a2 : a2;
+}
+
+// Per-face values that are the same on every lane.  Lane f < 6 of the
+// wavefront loads those of local face f at kernel start (one round of
+// dependent loads for all six faces); face_uniform() broadcasts them.
+template <class R>
+struct MetaV {
+    int F = 0, info = 0, nb = 0, fnon = 0, npn = 0;
+    int64_t fo = 0, to = 0, xn = 0;
+    R tau = 0;
+};
+
+template <class R>
+struct FaceU {
+    int F, slot, nf, o, npf;
+    int nb, kn, sn, on, npn;
+    int64_t fo, to, xn;
+    R tau;
+};
+
+__device__ __forceinline__ int rl32(int v, int f) { return __builtin_amdgcn_readlane(v, f); }
+__device__ __forceinline__ int64_t rl64(int64_t v, int f) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffff), f);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), f);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double rlR(double v, int f) { return __longlong_as_double(rl64(__double_as_longlong(v), f)); }
+__device__ __forceinline__ float rlR(float v, int f) { return __int_as_float(rl32(__float_as_int(v), f)); }
+
+template <class R, int MODE>
+__device__ __forceinline__ MetaV<R> load_meta(const Args &A, const Data<R> &D, int64_t e) {
+    MetaV<R> m;
+    const int l = threadIdx.x;
+    if (l < 6) {
+        const FaceRef fr = A.eface[e * 6 + l];
+        m.F = fr.F;
+        m.info = fr.info;
+        m.fo = A.foff[fr.F];
+        m.tau = D.tau[fr.F];
+        const int slot = face_slot(fr.info);
+        if (slot != 2) {
+            if (MODE == 2) {
+                const FaceTopo ft = A.faces[fr.F];
+                m.nb = slot == 0 ? ft.eR : ft.eL;
+                const int fn = slot == 0 ? ft.fR : ft.fL;
+                const int on = slot == 0 ? ft.orient : 0;
+                m.fnon = fn | (on << 3);
+                m.npn = A.order[m.nb] + 1;
+                m.xn = A.xoff[m.nb];
+            } else {
+                m.to = A.toff[fr.F];
+            }
+        }
+    }
+    return m;
+}
+
+template <class R>
+__device__ __forceinline__ FaceU<R> face_uniform(const MetaV<R> &m, int f) {
+    FaceU<R> u;
+    u.F = rl32(m.F, f);
+    const int info = rl32(m.info, f);
+    u.slot = face_slot(info);
+    u.nf = face_nf(info);
+    u.o = face_orient(info);
+    u.npf = u.nf * u.nf;
+    u.nb = rl32(m.nb, f);
+    const int fnon = rl32(m.fnon, f);
+    u.kn = (fnon & 7) >> 1;
+    u.sn = fnon & 1;
+    u.on = fnon >> 3;
+    u.npn = rl32(m.npn, f);
+    u.fo = rl64(m.fo, f);
+    u.to = rl64(m.to, f);
+    u.xn = rl64(m.xn, f);
+    u.tau = rlR(m.tau, f);
+    return u;
+}
+
+// Per-lane data of one face at this lane's trace point (t1, t2) in the
+// element's own face coordinates: the canonical index, a = w J_s, the
+// element's C along its (k, a, b) directions, and
+//   MODE 1: the neighbour's (u, g) from the trace buffer,
+//   MODE 2: the neighbour's C along its own (k, a, b) directions.
+template <class R>
+struct FaceD {
+    int qc;
+    R aw, Ck, Ca, Cb, n0, n1, n2;
+};
+
+template <class R, int MODE>
+__device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &u, int k) {
+    FaceD<R> d;
+    d.qc = 0;
+    d.aw = d.Ck = d.Ca = d.Cb = d.n0 = d.n1 = d.n2 = R(0);
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    if (t1 >= u.nf || t2 >= u.nf) return d;
+    if (MODE == 0 && u.slot == 2) return d;
+    const int npf = u.npf;
+    d.qc = canon_index(u.o, u.nf, t1, t2);
+    const R *__restrict__ fg = D.fgeo + u.fo;
+    const R *__restrict__ Co = fg + npf * (u.slot == 1 ? 4 : 1) + d.qc;
+    d.Ck = Co[k * npf];
+    d.Ca = Co[dir_a(k) * npf];
+    d.Cb = Co[dir_b(k) * npf];
+    if (MODE == 0) return d;
+    d.aw = fg[d.qc];
+    if (u.slot == 2) return d;
+    if (MODE == 1) {
+        const R *__restrict__ tb = D.tbuf + u.to + (1 - u.slot) * 2 * npf + d.qc;
+        d.n0 = tb[0];
+        d.n1 = tb[npf];
+    } else {
+        const R *__restrict__ Cn = fg + npf * (u.slot == 0 ? 4 : 1) + d.qc;
+        d.n0 = Cn[u.kn * npf];
+        d.n1 = Cn[dir_a(u.kn) * npf];
+        d.n2 = Cn[dir_b(u.kn) * npf];
+    }
+    return d;
+}
+
+// Own u, grad_xi u at trace point (t1, t2): the face point itself when the
+// trace has the element's points, else interpolated with I (n_F x n) along
+// both face directions through LDS.
+template <class R, int P>
+__device__ __forceinline__ void own_trace(const Data<R> &D, int nf, R *sm, R &u, R &dk, R &da, R &db) {
+    constexpr int N = P + 2;
+    if (nf == N) return;
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
+    const R *__restrict__ I = D.tab + tab_off_I(N, nf);  // [nf][N]
+    if (t1 < N && t2 < N) {
+        IS[l] = u;
+        IS[W + l] = dk;
+        IS[2 * W + l] = da;
+        IS[3 * W + l] = db;
+    }
+    __syncthreads();
+    if (t1 < nf && t2 < N) {
+        R c[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const R w = I[t1 * N + j];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) c[f] += w * IS[f * W + j + 8 * t2];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) IT[f * W + l] = c[f];
+    }
+    __syncthreads();
+    R c[4] = {0, 0, 0, 0};
+    if (t1 < nf && t2 < nf) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const R w = I[t2 * N + j];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) c[f] += w * IT[f * W + t1 + 8 * j];
+        }
+    }
+    u = c[0];
+    dk = c[1];
+    da = c[2];
+    db = c[3];
+    __syncthreads();
+}
+
+// Neighbour's u and g = C_n . grad_xi u_n at this lane's trace point, from its
+// coefficients (TracePhysEval in the neighbour's face coordinates).
+template <class R>
+__device__ __forceinline__ void nbr_trace(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R *sm,
+                                          R &un, R &gn) {
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    const int nf = fu.nf, npn = fu.npn, kn = fu.kn, sn = fu.sn;
+    R *NU = sm + NU_OFF, *NW = sm + NW_OFF;
+    const R *__restrict__ xn = D.x + fu.xn;
+    if (t1 < npn && t2 < npn) {
+        R v0 = 0, v1 = 0;
+#pragma unroll
+        for (int ik = 0; ik < 7; ++ik) {
+            if (ik < npn) {
+                const R xv = xn[mode_rt(npn, kn, t1, t2, ik)];
+                v0 += end_val<R>(ik, sn) * xv;
+                v1 += end_der<R>(ik, sn) * xv;
+            }
+        }
+        NU[l] = v0;
+        NU[W + l] = v1;
+    }
+    __syncthreads();
+    const R *__restrict__ BF = D.tab + tab_off_BF(nf);
+    const R *__restrict__ DBF = D.tab + tab_off_DBF(nf);
+    if (t1 < nf && t2 < npn) {
+        R w0 = 0, w0d = 0, w1 = 0;
+#pragma unroll
+        for (int ia = 0; ia < 7; ++ia) {
+            if (ia < npn) {
+                const R bv = BF[t1 * S9 + ia], dv = DBF[t1 * S9 + ia];
+                const R x0 = NU[ia + 8 * t2], x1 = NU[W + ia + 8 * t2];
+                w0 += bv * x0;
+                w0d += dv * x0;
+                w1 += bv * x1;
+            }
+        }
+        NW[l] = w0;
+        NW[W + l] = w0d;
+        NW[2 * W + l] = w1;
+    }
+    __syncthreads();
+    un = gn = 0;
+    if (t1 < nf && t2 < nf) {
+        int r1, r2;
+        canon_inverse(fu.on, nf, fd.qc, r1, r2);
+        R vu = 0, vda = 0, vdb = 0, vdk = 0;
+#pragma unroll
+        for (int ib = 0; ib < 7; ++ib) {
+            if (ib < npn) {
+                const R bv = BF[r2 * S9 + ib], dv = DBF[r2 * S9 + ib];
+                const R w0 = NW[r1 + 8 * ib], w0d = NW[W + r1 + 8 * ib], w1 = NW[2 * W + r1 + 8 * ib];
+                vu += bv * w0;
+                vda += bv * w0d;
+                vdb += dv * w0;
+                vdk += bv * w1;
+            }
+        }
+        un = vu;
+        gn = fd.n0 * vdk + fd.n1 * vda + fd.n2 * vdb;
+    }
+    __syncthreads();
+}
+
+// Lift of the flux of one face at this lane's own face point.  In: the
+// element's u, d_k u, d_a u, d_b u at its face point (a, b) = lane (valid for
+// a, b < n).  Out: L = (F_v, F_g C_k, F_g C_a, F_g C_b) at the same point, the
+// terms that multiply phi and d_k phi, d_a phi, d_b phi.
+template <class R, int P, int MODE>
+__device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R ou,
+                                          R odk, R oda, R odb, R *sm, R L[4]) {
+    constexpr int N = P + 2;
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    const int nf = fu.nf;
+    const bool tin = t1 < nf && t2 < nf;
+    R u = ou, dk = odk, da = oda, db = odb;
+    own_trace<R, P>(D, nf, sm, u, dk, da, db);
+    const R g = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
+    R un, gn;
+    if (fu.slot == 2) {
+        un = -u;   // mirrored exterior state
+        gn = -g;
+    } else if (MODE == 1) {
+        un = fd.n0;
+        gn = fd.n1;
+    } else {
+        nbr_trace<R>(D, fu, fd, sm, un, gn);
+    }
+    // flux of eq. IP at the trace point, this side's test terms
+    R Fv = 0, Fg = 0;
+    if (tin) {
+        const R jump = u - un;
+        Fv = R(-0.5) * (g - gn) + fu.tau * fd.aw * jump;
+        Fg = R(-0.5) * jump;
+    }
+    L[0] = Fv;
+    L[1] = Fg * fd.Ck;
+    L[2] = Fg * fd.Ca;
+    L[3] = Fg * fd.Cb;
+    if (nf != N) {
+        // transposed interpolation back to the element's face points
+        R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
+        const R *__restrict__ I = D.tab + tab_off_I(N, nf);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) IT[f * W + l] = L[f];
+        __syncthreads();
+        if (t1 < nf && t2 < N) {
+            R c[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < nf) {
+                    const R w = I[t * N + t2];
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) c[f] += w * IT[f * W + t1 + 8 * t];
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 4; ++f) IS[f * W + l] = c[f];
+        }
+        __syncthreads();
+        R c[4] = {0, 0, 0, 0};
+        if (t1 < N && t2 < N) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < nf) {
+                    const R w = I[t * N + t1];
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) c[f] += w * IS[f * W + t + 8 * t2];
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) L[f] = c[f];
+        __syncthreads();
+    }
+}
+
+// Trace of one interior face of this element: (u, g) at the trace points in
+// canonical order, into the trace buffer (this side's slot).
+template <class R, int P>
+__device__ __forceinline__ void face_store(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R ou, R odk,
+                                           R oda, R odb, R *sm) {
+    if (fu.slot == 2) return;
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R u = ou, dk = odk, da = oda, db = odb;
+    own_trace<R, P>(D, fu.nf, sm, u, dk, da, db);
+    if (t1 < fu.nf && t2 < fu.nf) {
+        R *__restrict__ tb = D.tbuf + fu.to + fu.slot * 2 * fu.npf + fd.qc;
+        tb[0] = u;
+        tb[fu.npf] = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
+    }
+}
+
+// MODE 0 (trace kernel): (u, g) of every interior face of the element into
+//   the trace buffer.
+// MODE 1 (apply, two-stage): y = A x with the neighbours' (u, g) read from the
+//   trace buffer written by MODE 0.
+// MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
+template <class R, int P, int MODE>
+__global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
+    using S = Sz<P>;
+    constexpr int N = S::N, NP = S::NP, NPTS = S::NPTS;
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *SA = reinterpret_cast<R *>(smem_raw);
+    R *SB = SA + S::ARR;
+    R *FB = SA + FB_OFF;
+    const int64_t e = A.elems[blockIdx.x];
+    const int l = threadIdx.x, a = l & 7, b = l >> 3;
+    const bool col = a < N && b < N;
+    const ctab<R> Bt = as_const(D.tab) + tab_off_B(P);   // [N][NP]
+    const ctab<R> Dt = as_const(D.tab) + tab_off_D(N);   // [N][N]
+    const int64_t xo = A.xoff[e];
+    const MetaV<R> meta = load_meta<R, MODE>(A, D, e);
+
+    // BwdTrans along xi_0: lane (i1, i2)
+    if (a < NP && b < NP) {
+        const R *__restrict__ xe = D.x + xo + NP * (a + NP * b);
+        R v[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) v[i] = xe[i];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R s = 0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) s += Bt[q * NP + i] * v[i];
+            SA[pa<P>(q, a, b)] = s;
+        }
+    }
+    __syncthreads();
+    // along xi_1: lane (q0, i2)
+    if (a < N && b < NP) {
+        R v[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) v[i] = SA[pa<P>(a, i, b)];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R s = 0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) s += Bt[q * NP + i] * v[i];
+            SB[pa<P>(a, q, b)] = s;
+        }
+    }
+    __syncthreads();
+    // along xi_2 into the column, and d_2 u in the column
+    R u[N], d0[N], d1[N], d2[N];
+    if (col) {
+        R v[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) v[i] = SB[pa<P>(a, b, i)];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R s = 0;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) s += Bt[q * NP + i] * v[i];
+            u[q] = s;
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R s = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) s += Dt[q * N + j] * u[j];
+            d2[q] = s;
+        }
+    }
+    __syncthreads();
+    if (col) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            SA[pa<P>(a, b, q)] = u[q];
+            SB[pa<P>(a, b, q)] = d2[q];
+        }
+    }
+    __syncthreads();
+    // d_0 u on line-0 lanes (q1, q2) = (a, b), d_1 u on line-1 lanes (q0, q2) = (a, b);
+    // keep the faces' values at the line ends
+    R x_u[2], x_dk[2], x_da[2], x_db[2];   // faces normal to xi_0 at (q1, q2) = (a, b)
+    R y_u[2], y_dk[2], y_da[2], y_db[2];   // faces normal to xi_1 at (q0, q2) = (a, b)
+    R l0[N], l1[N];
+    if (col) {
+        R v[N], w[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            v[j] = SA[pa<P>(j, a, b)];
+            w[j] = SA[pa<P>(a, j, b)];
+        }
+        x_db[0] = SB[pa<P>(0, a, b)];
+        x_db[1] = SB[pa<P>(N - 1, a, b)];
+        y_db[0] = SB[pa<P>(a, 0, b)];
+        y_db[1] = SB[pa<P>(a, N - 1, b)];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            R s = 0, t = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                s += Dt[q * N + j] * v[j];
+                t += Dt[q * N + j] * w[j];
+            }
+            l0[q] = s;
+            l1[q] = t;
+        }
+        x_u[0] = v[0];
+        x_u[1] = v[N - 1];
+        x_dk[0] = l0[0];
+        x_dk[1] = l0[N - 1];
+        y_u[0] = w[0];
+        y_u[1] = w[N - 1];
+        y_dk[0] = l1[0];
+        y_dk[1] = l1[N - 1];
+    }
+    __syncthreads();
+    if (col) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            SA[pa<P>(q, a, b)] = l0[q];
+            SB[pa<P>(a, q, b)] = l1[q];
+        }
+    }
+    __syncthreads();
+    R z_u[2], z_dk[2], z_da[2], z_db[2];   // faces normal to xi_2 at (q0, q1) = (a, b)
+    if (MODE != 0 && col) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            d0[q] = SA[pa<P>(a, b, q)];
+            d1[q] = SB[pa<P>(a, b, q)];
+        }
+    }
+    if (col) {
+        x_da[0] = SB[pa<P>(0, a, b)];
+        x_da[1] = SB[pa<P>(N - 1, a, b)];
+        y_da[0] = SA[pa<P>(a, 0, b)];
+        y_da[1] = SA[pa<P>(a, N - 1, b)];
+        z_u[0] = u[0];
+        z_u[1] = u[N - 1];
+        z_dk[0] = d2[0];
+        z_dk[1] = d2[N - 1];
+        z_da[0] = SA[pa<P>(a, b, 0)];
+        z_da[1] = SA[pa<P>(a, b, N - 1)];
+        z_db[0] = SB[pa<P>(a, b, 0)];
+        z_db[1] = SB[pa<P>(a, b, N - 1)];
+    }
+    __syncthreads();
+
+    // local faces in processing order: normal to xi_2, then xi_0, then xi_1
+    if (MODE == 0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const FaceU<R> fu = face_uniform<R>(meta, 4 + s);
+            const FaceD<R> fd = load_face<R, 0>(D, fu, 2);
+            face_store<R, P>(D, fu, fd, z_u[s], z_dk[s], z_da[s], z_db[s], SA);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const FaceU<R> fu = face_uniform<R>(meta, s);
+            const FaceD<R> fd = load_face<R, 0>(D, fu, 0);
+            face_store<R, P>(D, fu, fd, x_u[s], x_dk[s], x_da[s], x_db[s], SA);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const FaceU<R> fu = face_uniform<R>(meta, 2 + s);
+            const FaceD<R> fd = load_face<R, 0>(D, fu, 1);
+            face_store<R, P>(D, fu, fd, y_u[s], y_dk[s], y_da[s], y_db[s], SA);
+        }
+        return;
+    }
+
+    // per-point face data of the first faces, in flight during the pointwise terms
+    FaceU<R> fu4 = face_uniform<R>(meta, 4);
+    FaceD<R> fd4 = load_face<R, MODE>(D, fu4, 2);
+    FaceU<R> fu5 = face_uniform<R>(meta, 5);
+    FaceD<R> fd5 = load_face<R, MODE>(D, fu5, 2);
+
+    // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q)
+    if (col) {
+        const R *__restrict__ vg = D.vgeo + A.voff[e];
+        const R lam = D.lam[e];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const int p = a + N * (b + N * q);
+            const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
+            const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
+            const R wj = vg[6 * NPTS + p];
+            const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
+            u[q] = lam * wj * u[q];
+            d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
+            d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
+            d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
+        }
+    }
+
+    FaceU<R> fu0 = face_uniform<R>(meta, 0);
+    FaceD<R> fd0 = load_face<R, MODE>(D, fu0, 0);
+    FaceU<R> fu1 = face_uniform<R>(meta, 1);
+    FaceD<R> fd1 = load_face<R, MODE>(D, fu1, 0);
+    // faces normal to xi_2: own points are the column ends
+    {
+        R L[4];
+        face_lift<R, P, MODE>(D, fu4, fd4, z_u[0], z_dk[0], z_da[0], z_db[0], SA, L);
+        if (col) {
+            u[0] += L[0];
+            d2[0] += L[1];
+            d0[0] += L[2];
+            d1[0] += L[3];
+        }
+        face_lift<R, P, MODE>(D, fu5, fd5, z_u[1], z_dk[1], z_da[1], z_db[1], SA, L);
+        if (col) {
+            u[N - 1] += L[0];
+            d2[N - 1] += L[1];
+            d0[N - 1] += L[2];
+            d1[N - 1] += L[3];
+        }
+    }
+    FaceU<R> fu2 = face_uniform<R>(meta, 2);
+    FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
+    FaceU<R> fu3 = face_uniform<R>(meta, 3);
+    FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
+    // faces normal to xi_0: own points on line-0 lanes; lifted values go to the
+    // column lanes q0 = 0, n-1 through FB
+    {
+        R L[4];
+        face_lift<R, P, MODE>(D, fu0, fd0, x_u[0], x_dk[0], x_da[0], x_db[0], SA, L);
+        if (col) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
+        }
+        face_lift<R, P, MODE>(D, fu1, fd1, x_u[1], x_dk[1], x_da[1], x_db[1], SA, L);
+        if (col) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
+        }
+    }
+    __syncthreads();
+    if (col && (a == 0 || a == N - 1)) {
+        const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            u[q] += fb[8 * q];
+            d0[q] += fb[W + 8 * q];
+            d1[q] += fb[2 * W + 8 * q];
+            d2[q] += fb[3 * W + 8 * q];
+        }
+    }
+    __syncthreads();
+    // faces normal to xi_1: own points on line-1 lanes (q0, q2)
+    {
+        R L[4];
+        face_lift<R, P, MODE>(D, fu2, fd2, y_u[0], y_dk[0], y_da[0], y_db[0], SA, L);
+        if (col) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
+        }
+        face_lift<R, P, MODE>(D, fu3, fd3, y_u[1], y_dk[1], y_da[1], y_db[1], SA, L);
+        if (col) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
+        }
+    }
+    __syncthreads();
+    if (col && (b == 0 || b == N - 1)) {
+        const R *fb = FB + (b == 0 ? 0 : 4 * W) + a;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            u[q] += fb[8 * q];
+            d1[q] += fb[W + 8 * q];
+            d0[q] += fb[2 * W + 8 * q];
+            d2[q] += fb[3 * W + 8 * q];
+        }
+    }
+    __syncthreads();
+
+    // IProduct: y = B^T (m + D_0^T q_0 + D_1^T q_1 + D_2^T q_2)
+    R z[N];
+    if (col) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            SA[pa<P>(a, b, q)] = d0[q];
+            SB[pa<P>(a, b, q)] = d1[q];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            R s = u[j];
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += Dt[q * N + j] * d2[q];
+            z[j] = s;
+        }
+    }
+    __syncthreads();
+    if (col) {
+        R v[N], w[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            v[j] = SA[pa<P>(j, a, b)];
+            w[j] = SB[pa<P>(a, j, b)];
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            R s = 0, t = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                s += Dt[q * N + j] * v[q];
+                t += Dt[q * N + j] * w[q];
+            }
+            l0[j] = s;
+            l1[j] = t;
+        }
+    }
+    __syncthreads();
+    if (col) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            SA[pa<P>(q, a, b)] = l0[q];
+            SB[pa<P>(a, q, b)] = l1[q];
+        }
+    }
+    __syncthreads();
+    R w2[NP];
+    if (col) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) z[q] += SA[pa<P>(a, b, q)] + SB[pa<P>(a, b, q)];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            R s = 0;
+#pragma unroll
+            for (int q = 0; q < N; ++q) s += Bt[q * NP + i] * z[q];
+            w2[i] = s;
+        }
+    }
+    __syncthreads();
+    if (col) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) SA[pa<P>(a, b, i)] = w2[i];
+    }
+    __syncthreads();
+    // B^T along xi_1: lane (q0, i2)
+    if (a < N && b < NP) {
+        R v[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = SA[pa<P>(a, j, b)];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            R s = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) s += Bt[j * NP + i] * v[j];
+            SB[pa<P>(a, i, b)] = s;
+        }
+    }
+    __syncthreads();
+    // B^T along xi_0: lane (i1, i2), y written once
+    if (a < NP && b < NP) {
+        R v[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = SB[pa<P>(j, a, b)];
+        R *__restrict__ ye = D.y + xo + NP * (a + NP * b);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            R s = 0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) s += Bt[j * NP + i] * v[j];
+            ye[i] = s;
+        }
+    }
+}
+
+}  // namespace g3
+}  // namespace sipdg

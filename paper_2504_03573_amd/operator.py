@@ -167,7 +167,7 @@ class SipdgOperator:
 
     def autotune(self, reps: int = 20, stream=None) -> dict:
         """Time every allowed kernel structure and keep the fastest."""
-        ms = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * len(C.VARIANTS))()
         C.check(self._lib.sipdg_autotune(self._h, int(reps), ms, _stream_ptr(stream)))
         return {name: ms[i] for name, i in C.VARIANTS.items() if ms[i] > 0}
 

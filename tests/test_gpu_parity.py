@@ -152,8 +152,8 @@ def test_cg_f32_ir(case):
 def test_variants_agree(case):
     """Gather-and-interpolate and direct trace evaluation give the same
     operator (Sec. 3.2: equivalent when the trace order is at least the
-    element's); the fused and two-stage launch structures are identical
-    up to rounding."""
+    element's); the fused, two-stage and gather-fold launch structures are
+    identical up to rounding."""
     name, mesh, op, om = case
     if mesh.dim != 3 or int(mesh.order.max()) > 6:
         pytest.skip("direct trace-evaluation kernels cover 3-D orders <= 6")
@@ -163,7 +163,7 @@ def test_variants_agree(case):
     ys = {}
     keep = op.variant
     try:
-        for v in ("gather", "two_stage", "fused"):
+        for v in ("gather", "two_stage", "fused", "gather_fold", "gather_fold_fused"):
             op.variant = v
             ys[v] = op.apply(xt).cpu().numpy()
             assert rel(ys[v], y_ref) <= 1e-12, v
@@ -171,5 +171,7 @@ def test_variants_agree(case):
             assert rel(y32, y_ref) <= 1e-5, v
         assert rel(ys["fused"], ys["gather"]) <= 1e-13
         assert rel(ys["two_stage"], ys["fused"]) <= 1e-14
+        assert rel(ys["gather_fold"], ys["gather"]) <= 1e-13
+        assert rel(ys["gather_fold_fused"], ys["gather_fold"]) <= 1e-14
     finally:
         op.variant = keep
