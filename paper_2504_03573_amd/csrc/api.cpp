@@ -127,7 +127,8 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 f3::Args3 A3;
                 f3::Data3<R> D3;
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
-                g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff, A3.skip};
+                g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
+                           A3.skip, g.d_desc, g.d_fdesc};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
                 hipError_t e = launch_gfold3d<R>(g.P, mode, A, D, st);
                 if (e != hipSuccess)
@@ -210,8 +211,11 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_dinv64, c->d_dinv32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    for (Group &g : c->groups)
+    for (Group &g : c->groups) {
         if (g.d_elems) (void)hipFree(g.d_elems);
+        if (g.d_desc) (void)hipFree(g.d_desc);
+        if (g.d_fdesc) (void)hipFree(g.d_fdesc);
+    }
     free_cg(c);
     delete c;
 }
@@ -338,6 +342,20 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         g.d_elems = nullptr;
         TRY(upload(&g.d_elems, ids));
         c->groups.push_back(g);
+        if (T.dim == 3) {
+            std::vector<ElemDesc> desc(ids.size());
+            std::vector<FaceDesc> fdesc(ids.size() * 6);
+            for (size_t i = 0; i < ids.size(); ++i) {
+                const int64_t e = ids[i];
+                desc[i] = ElemDesc{T.xoff[e], T.voff[e], (int)e, 0};
+                for (int f = 0; f < 6; ++f) {
+                    const FaceRef fr = T.eface[(size_t)e * 6 + f];
+                    fdesc[i * 6 + f] = FaceDesc{T.foff[fr.F], T.toff[fr.F], fr.F, fr.info};
+                }
+            }
+            TRY(upload(&c->groups.back().d_desc, desc));
+            TRY(upload(&c->groups.back().d_fdesc, fdesc));
+        }
         // check the block fits in LDS
         hipDeviceProp_t prop;
         TRYHIP(hipGetDeviceProperties(&prop, c->device));

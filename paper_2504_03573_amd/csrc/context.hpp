@@ -44,7 +44,7 @@ struct OpArgs {
     const int64_t *voff;    // [ne] volume-factor offsets
     const FaceRef *eface;   // [ne][2 dim]
     const int64_t *foff;    // [nf] face-factor offsets
-    const int64_t *toff;    // [nf] trace-buffer offsets (-1 on boundary faces)
+    const int64_t *toff;    // [nf] trace-buffer offsets (interior: 2 sides, boundary: 1)
     const R *vgeo;          // volume factors
     const R *fgeo;          // face factors
     const R *lam;           // [ne]
@@ -56,11 +56,25 @@ struct OpArgs {
     const int *skip;        // optional: return at once when *skip != 0
 };
 
+// Per-element descriptors of an order group (3-D), indexed by the position in
+// the group, so that a kernel reaches its element's offsets and the records
+// of its six faces in one round of loads.
+struct ElemDesc {
+    int64_t xoff, voff;     // coefficient and volume-factor offsets
+    int e, pad;             // element id
+};
+struct FaceDesc {
+    int64_t fo, to;         // face-factor and trace-buffer offsets
+    int F, info;            // face id and FaceRef::info
+};
+
 struct Group {
     int P;
     int count;
-    int nfmax;              // largest trace size touching the group
+    int nfmax;              // largest trace that touches the group
     int *d_elems;
+    ElemDesc *d_desc = nullptr;      // [count]      (3-D)
+    FaceDesc *d_fdesc = nullptr;     // [count][6]   (3-D)
 };
 
 struct CgWork;  // defined in the solver

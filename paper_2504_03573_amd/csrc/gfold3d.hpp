@@ -48,15 +48,17 @@ struct Sz {
     static constexpr int S1 = 9;
     static constexpr int S2 = N >= 7 ? 72 : (N >= 5 ? 56 : (N == 4 ? 40 : 24));
     static constexpr int ARR = S2 * N;     // one padded point array
-    static constexpr int SCR = 1024;       // face scratch, aliases the point arrays
+    static constexpr int SCR = 1536;       // face scratch, aliases the point arrays
     static constexpr int TOTAL = 2 * ARR > SCR ? 2 * ARR : SCR;
 };
 
 // face scratch (R units from the block's LDS base):
-//   FB [2 sides][4 fields][64]   lifted flux of the faces normal to xi_0 / xi_1
+//   FB [2 directions][2 sides][4 fields][64]  lifted flux of the faces normal
+//                                to xi_0 and xi_1, held until the pointwise terms
 //   NU [2][64], NW [3][64]       neighbour trace evaluation
 //   IS [4][64], IT [4][64]       interpolation to / from a finer trace (aliases NU, NW)
-constexpr int FB_OFF = 0, NU_OFF = 512, NW_OFF = 640, IS_OFF = 512, IT_OFF = 768;
+constexpr int FB_OFF = 0, WK_OFF = 1024;
+constexpr int NU_OFF = WK_OFF, NW_OFF = WK_OFF + 128, IS_OFF = WK_OFF, IT_OFF = WK_OFF + 256;
 
 struct Args {
     const int *elems;
@@ -69,6 +71,8 @@ struct Args {
     const int64_t *foff;
     const int64_t *toff;
     const int *skip;
+    const ElemDesc *desc;    // [count]
+    const FaceDesc *fdesc;   // [count][6]
 };
 
 template <class R>
@@ -155,14 +159,15 @@ __device__ __forceinline__ double rlR(double v, int f) { return __longlong_as_do
 __device__ __forceinline__ float rlR(float v, int f) { return __int_as_float(rl32(__float_as_int(v), f)); }
 
 template <class R, int MODE>
-__device__ __forceinline__ MetaV<R> load_meta(const Args &A, const Data<R> &D, int64_t e) {
+__device__ __forceinline__ MetaV<R> load_meta(const Args &A, const Data<R> &D, int blk) {
     MetaV<R> m;
     const int l = threadIdx.x;
     if (l < 6) {
-        const FaceRef fr = A.eface[e * 6 + l];
+        const FaceDesc fr = A.fdesc[(int64_t)blk * 6 + l];
         m.F = fr.F;
         m.info = fr.info;
-        m.fo = A.foff[fr.F];
+        m.fo = fr.fo;
+        m.to = fr.to;
         m.tau = D.tau[fr.F];
         const int slot = face_slot(fr.info);
         if (slot != 2) {
@@ -174,8 +179,6 @@ __device__ __forceinline__ MetaV<R> load_meta(const Args &A, const Data<R> &D, i
                 m.fnon = fn | (on << 3);
                 m.npn = A.order[m.nb] + 1;
                 m.xn = A.xoff[m.nb];
-            } else {
-                m.to = A.toff[fr.F];
             }
         }
     }
@@ -207,22 +210,26 @@ __device__ __forceinline__ FaceU<R> face_uniform(const MetaV<R> &m, int f) {
 // Per-lane data of one face at this lane's trace point (t1, t2) in the
 // element's own face coordinates: the canonical index, a = w J_s, the
 // element's C along its (k, a, b) directions, and
-//   MODE 1: the neighbour's (u, g) from the trace buffer,
+//   MODE 1: the element's own (u, g) = (ou, og) and the neighbour's
+//           (n0, n1) from the trace buffer,
 //   MODE 2: the neighbour's C along its own (k, a, b) directions.
 template <class R>
 struct FaceD {
     int qc;
-    R aw, Ck, Ca, Cb, n0, n1, n2;
+    R aw, Ck, Ca, Cb, n0, n1, n2, ou, og;
 };
+
+// Trace-buffer position of a side: interior faces hold [owner][other],
+// boundary faces only the element's own.
+__device__ __forceinline__ int tb_side(int slot) { return slot == 1 ? 1 : 0; }
 
 template <class R, int MODE>
 __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &u, int k) {
     FaceD<R> d;
     d.qc = 0;
-    d.aw = d.Ck = d.Ca = d.Cb = d.n0 = d.n1 = d.n2 = R(0);
+    d.aw = d.Ck = d.Ca = d.Cb = d.n0 = d.n1 = d.n2 = d.ou = d.og = R(0);
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
     if (t1 >= u.nf || t2 >= u.nf) return d;
-    if (MODE == 0 && u.slot == 2) return d;
     const int npf = u.npf;
     d.qc = canon_index(u.o, u.nf, t1, t2);
     const R *__restrict__ fg = D.fgeo + u.fo;
@@ -232,12 +239,19 @@ __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &
     d.Cb = Co[dir_b(k) * npf];
     if (MODE == 0) return d;
     d.aw = fg[d.qc];
-    if (u.slot == 2) return d;
     if (MODE == 1) {
-        const R *__restrict__ tb = D.tbuf + u.to + (1 - u.slot) * 2 * npf + d.qc;
-        d.n0 = tb[0];
-        d.n1 = tb[npf];
-    } else {
+        const R *__restrict__ tb = D.tbuf + u.to + d.qc;
+        const int so = tb_side(u.slot);
+        d.ou = tb[so * 2 * npf];
+        d.og = tb[so * 2 * npf + npf];
+        if (u.slot != 2) {
+            d.n0 = tb[(1 - so) * 2 * npf];
+            d.n1 = tb[(1 - so) * 2 * npf + npf];
+        }
+        return d;
+    }
+    if (u.slot == 2) return d;
+    {
         const R *__restrict__ Cn = fg + npf * (u.slot == 0 ? 4 : 1) + d.qc;
         d.n0 = Cn[u.kn * npf];
         d.n1 = Cn[dir_a(u.kn) * npf];
@@ -256,6 +270,11 @@ __device__ __forceinline__ void own_trace(const Data<R> &D, int nf, R *sm, R &u,
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
     R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
     const R *__restrict__ I = D.tab + tab_off_I(N, nf);  // [nf][N]
+    // table rows of the first contraction first, so that their loads overlap
+    // the LDS exchange
+    R w1[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) w1[j] = t1 < nf ? I[t1 * N + j] : R(0);
     if (t1 < N && t2 < N) {
         IS[l] = u;
         IS[W + l] = dk;
@@ -267,21 +286,22 @@ __device__ __forceinline__ void own_trace(const Data<R> &D, int nf, R *sm, R &u,
         R c[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const R w = I[t1 * N + j];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w * IS[f * W + j + 8 * t2];
+            for (int f = 0; f < 4; ++f) c[f] += w1[j] * IS[f * W + j + 8 * t2];
         }
 #pragma unroll
         for (int f = 0; f < 4; ++f) IT[f * W + l] = c[f];
     }
+    R w2[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) w2[j] = t2 < nf ? I[t2 * N + j] : R(0);
     __syncthreads();
     R c[4] = {0, 0, 0, 0};
     if (t1 < nf && t2 < nf) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
-            const R w = I[t2 * N + j];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w * IT[f * W + t1 + 8 * j];
+            for (int f = 0; f < 4; ++f) c[f] += w2[j] * IT[f * W + t1 + 8 * j];
         }
     }
     u = c[0];
@@ -366,9 +386,16 @@ __device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, 
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
     const int nf = fu.nf;
     const bool tin = t1 < nf && t2 < nf;
-    R u = ou, dk = odk, da = oda, db = odb;
-    own_trace<R, P>(D, nf, sm, u, dk, da, db);
-    const R g = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
+    R u, g;
+    if (MODE == 1) {
+        u = fd.ou;
+        g = fd.og;
+    } else {
+        R dk = odk, da = oda, db = odb;
+        u = ou;
+        own_trace<R, P>(D, nf, sm, u, dk, da, db);
+        g = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
+    }
     R un, gn;
     if (fu.slot == 2) {
         un = -u;   // mirrored exterior state
@@ -394,6 +421,9 @@ __device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, 
         // transposed interpolation back to the element's face points
         R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
         const R *__restrict__ I = D.tab + tab_off_I(N, nf);
+        R c1[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) c1[t] = (t < nf && t2 < N) ? I[t * N + t2] : R(0);
 #pragma unroll
         for (int f = 0; f < 4; ++f) IT[f * W + l] = L[f];
         __syncthreads();
@@ -402,23 +432,24 @@ __device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, 
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 if (t < nf) {
-                    const R w = I[t * N + t2];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += w * IT[f * W + t1 + 8 * t];
+                    for (int f = 0; f < 4; ++f) c[f] += c1[t] * IT[f * W + t1 + 8 * t];
                 }
             }
 #pragma unroll
             for (int f = 0; f < 4; ++f) IS[f * W + l] = c[f];
         }
+        R c2[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) c2[t] = (t < nf && t1 < N) ? I[t * N + t1] : R(0);
         __syncthreads();
         R c[4] = {0, 0, 0, 0};
         if (t1 < N && t2 < N) {
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 if (t < nf) {
-                    const R w = I[t * N + t1];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += w * IS[f * W + t + 8 * t2];
+                    for (int f = 0; f < 4; ++f) c[f] += c2[t] * IS[f * W + t + 8 * t2];
                 }
             }
         }
@@ -428,29 +459,29 @@ __device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, 
     }
 }
 
-// Trace of one interior face of this element: (u, g) at the trace points in
-// canonical order, into the trace buffer (this side's slot).
+// Trace of one face of this element: (u, g) at the trace points in canonical
+// order, into the trace buffer (this side's slot).
 template <class R, int P>
 __device__ __forceinline__ void face_store(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R ou, R odk,
                                            R oda, R odb, R *sm) {
-    if (fu.slot == 2) return;
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
     R u = ou, dk = odk, da = oda, db = odb;
     own_trace<R, P>(D, fu.nf, sm, u, dk, da, db);
     if (t1 < fu.nf && t2 < fu.nf) {
-        R *__restrict__ tb = D.tbuf + fu.to + fu.slot * 2 * fu.npf + fd.qc;
+        R *__restrict__ tb = D.tbuf + fu.to + tb_side(fu.slot) * 2 * fu.npf + fd.qc;
         tb[0] = u;
         tb[fu.npf] = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
     }
 }
 
-// MODE 0 (trace kernel): (u, g) of every interior face of the element into
-//   the trace buffer.
-// MODE 1 (apply, two-stage): y = A x with the neighbours' (u, g) read from the
-//   trace buffer written by MODE 0.
+// MODE 0 (trace kernel): (u, g) of every face side of the element at the trace
+//   points into the trace buffer.
+// MODE 1 (apply, two-stage): y = A x with both sides' (u, g) read from the
+//   trace buffer written by MODE 0 (the element's own face values and their
+//   interpolation are not needed again).
 // MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
 template <class R, int P, int MODE>
-__global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g(Args A, Data<R> D) {
     using S = Sz<P>;
     constexpr int N = S::N, NP = S::NP, NPTS = S::NPTS;
     if (A.skip && *A.skip) return;
@@ -458,13 +489,24 @@ __global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
     R *SA = reinterpret_cast<R *>(smem_raw);
     R *SB = SA + S::ARR;
     R *FB = SA + FB_OFF;
-    const int64_t e = A.elems[blockIdx.x];
+    const ElemDesc ed = A.desc[blockIdx.x];
+    const int64_t e = ed.e;
     const int l = threadIdx.x, a = l & 7, b = l >> 3;
     const bool col = a < N && b < N;
     const ctab<R> Bt = as_const(D.tab) + tab_off_B(P);   // [N][NP]
     const ctab<R> Dt = as_const(D.tab) + tab_off_D(N);   // [N][N]
-    const int64_t xo = A.xoff[e];
-    const MetaV<R> meta = load_meta<R, MODE>(A, D, e);
+    const int64_t xo = ed.xoff;
+    const MetaV<R> meta = load_meta<R, MODE>(A, D, blockIdx.x);
+    // trace kernel: every face's per-point data in flight from the start
+    FaceU<R> tu[MODE == 0 ? 6 : 1];
+    FaceD<R> td[MODE == 0 ? 6 : 1];
+    if (MODE == 0) {
+#pragma unroll
+        for (int f = 0; f < (MODE == 0 ? 6 : 0); ++f) {
+            tu[f] = face_uniform<R>(meta, f);
+            td[f] = load_face<R, 0>(D, tu[f], f >> 1);
+        }
+    }
 
     // BwdTrans along xi_0: lane (i1, i2)
     if (a < NP && b < NP) {
@@ -525,6 +567,15 @@ __global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
         }
     }
     __syncthreads();
+    // apply kernels: the first faces' per-point data in flight during the line phases
+    FaceU<R> fu0, fu1;
+    FaceD<R> fd0, fd1;
+    if (MODE != 0) {
+        fu0 = face_uniform<R>(meta, 0);
+        fd0 = load_face<R, MODE>(D, fu0, 0);
+        fu1 = face_uniform<R>(meta, 1);
+        fd1 = load_face<R, MODE>(D, fu1, 0);
+    }
     // d_0 u on line-0 lanes (q1, q2) = (a, b), d_1 u on line-1 lanes (q0, q2) = (a, b);
     // keep the faces' values at the line ends
     R x_u[2], x_dk[2], x_da[2], x_db[2];   // faces normal to xi_0 at (q1, q2) = (a, b)
@@ -594,38 +645,50 @@ __global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
     }
     __syncthreads();
 
-    // local faces in processing order: normal to xi_2, then xi_0, then xi_1
     if (MODE == 0) {
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const FaceU<R> fu = face_uniform<R>(meta, 4 + s);
-            const FaceD<R> fd = load_face<R, 0>(D, fu, 2);
-            face_store<R, P>(D, fu, fd, z_u[s], z_dk[s], z_da[s], z_db[s], SA);
-        }
+        for (int s = 0; s < 2; ++s)
+            face_store<R, P>(D, tu[4 + s], td[4 + s], z_u[s], z_dk[s], z_da[s], z_db[s], SA);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const FaceU<R> fu = face_uniform<R>(meta, s);
-            const FaceD<R> fd = load_face<R, 0>(D, fu, 0);
-            face_store<R, P>(D, fu, fd, x_u[s], x_dk[s], x_da[s], x_db[s], SA);
-        }
+        for (int s = 0; s < 2; ++s)
+            face_store<R, P>(D, tu[s], td[s], x_u[s], x_dk[s], x_da[s], x_db[s], SA);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const FaceU<R> fu = face_uniform<R>(meta, 2 + s);
-            const FaceD<R> fd = load_face<R, 0>(D, fu, 1);
-            face_store<R, P>(D, fu, fd, y_u[s], y_dk[s], y_da[s], y_db[s], SA);
-        }
+        for (int s = 0; s < 2; ++s)
+            face_store<R, P>(D, tu[2 + s], td[2 + s], y_u[s], y_dk[s], y_da[s], y_db[s], SA);
         return;
     }
 
-    // per-point face data of the first faces, in flight during the pointwise terms
-    FaceU<R> fu4 = face_uniform<R>(meta, 4);
-    FaceD<R> fd4 = load_face<R, MODE>(D, fu4, 2);
-    FaceU<R> fu5 = face_uniform<R>(meta, 5);
-    FaceD<R> fd5 = load_face<R, MODE>(D, fu5, 2);
+    // faces normal to xi_0 and xi_1 first (their own values sit on line lanes);
+    // the lifted flux waits in FB until the pointwise terms exist.  The next
+    // face's per-point data is always in flight while one face is processed.
+    {
+        R L[4];
+        const FaceU<R> fu2 = face_uniform<R>(meta, 2);
+        const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
+        face_lift<R, P, MODE>(D, fu0, fd0, x_u[0], x_dk[0], x_da[0], x_db[0], SA, L);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
+        const FaceU<R> fu3 = face_uniform<R>(meta, 3);
+        const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
+        face_lift<R, P, MODE>(D, fu1, fd1, x_u[1], x_dk[1], x_da[1], x_db[1], SA, L);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
+        fu0 = face_uniform<R>(meta, 4);
+        fd0 = load_face<R, MODE>(D, fu0, 2);
+        face_lift<R, P, MODE>(D, fu2, fd2, y_u[0], y_dk[0], y_da[0], y_db[0], SA, L);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) FB[512 + f * W + l] = L[f];
+        face_lift<R, P, MODE>(D, fu3, fd3, y_u[1], y_dk[1], y_da[1], y_db[1], SA, L);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) FB[512 + 4 * W + f * W + l] = L[f];
+    }
+    FaceU<R> fu4 = fu0;
+    FaceD<R> fd4 = fd0;
 
-    // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q)
+    // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
+    // in chunks, so that the factor loads of one chunk are in flight together
     if (col) {
-        const R *__restrict__ vg = D.vgeo + A.voff[e];
+        const R *__restrict__ vg = D.vgeo + ed.voff;
         const R lam = D.lam[e];
 #pragma unroll
         for (int q = 0; q < N; ++q) {
@@ -638,16 +701,15 @@ __global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
             d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
             d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
             d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
+            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
     }
 
-    FaceU<R> fu0 = face_uniform<R>(meta, 0);
-    FaceD<R> fd0 = load_face<R, MODE>(D, fu0, 0);
-    FaceU<R> fu1 = face_uniform<R>(meta, 1);
-    FaceD<R> fd1 = load_face<R, MODE>(D, fu1, 0);
     // faces normal to xi_2: own points are the column ends
     {
         R L[4];
+        const FaceU<R> fu5 = face_uniform<R>(meta, 5);
+        const FaceD<R> fd5 = load_face<R, MODE>(D, fu5, 2);
         face_lift<R, P, MODE>(D, fu4, fd4, z_u[0], z_dk[0], z_da[0], z_db[0], SA, L);
         if (col) {
             u[0] += L[0];
@@ -663,26 +725,9 @@ __global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
             d1[N - 1] += L[3];
         }
     }
-    FaceU<R> fu2 = face_uniform<R>(meta, 2);
-    FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
-    FaceU<R> fu3 = face_uniform<R>(meta, 3);
-    FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
-    // faces normal to xi_0: own points on line-0 lanes; lifted values go to the
-    // column lanes q0 = 0, n-1 through FB
-    {
-        R L[4];
-        face_lift<R, P, MODE>(D, fu0, fd0, x_u[0], x_dk[0], x_da[0], x_db[0], SA, L);
-        if (col) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
-        }
-        face_lift<R, P, MODE>(D, fu1, fd1, x_u[1], x_dk[1], x_da[1], x_db[1], SA, L);
-        if (col) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
-        }
-    }
     __syncthreads();
+    // lifted flux of the faces normal to xi_0 (column lanes q0 = 0, n-1) and
+    // xi_1 (column lanes q1 = 0, n-1)
     if (col && (a == 0 || a == N - 1)) {
         const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
 #pragma unroll
@@ -693,24 +738,8 @@ __global__ __launch_bounds__(W) void k3g(Args A, Data<R> D) {
             d2[q] += fb[3 * W + 8 * q];
         }
     }
-    __syncthreads();
-    // faces normal to xi_1: own points on line-1 lanes (q0, q2)
-    {
-        R L[4];
-        face_lift<R, P, MODE>(D, fu2, fd2, y_u[0], y_dk[0], y_da[0], y_db[0], SA, L);
-        if (col) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
-        }
-        face_lift<R, P, MODE>(D, fu3, fd3, y_u[1], y_dk[1], y_da[1], y_db[1], SA, L);
-        if (col) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
-        }
-    }
-    __syncthreads();
     if (col && (b == 0 || b == N - 1)) {
-        const R *fb = FB + (b == 0 ? 0 : 4 * W) + a;
+        const R *fb = FB + 512 + (b == 0 ? 0 : 4 * W) + a;
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             u[q] += fb[8 * q];

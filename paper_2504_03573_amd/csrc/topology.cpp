@@ -262,6 +262,8 @@ int build_topology(int nprob, const sipdg_mesh_desc *descs, Topology &T, std::st
             T.orient_count[r.orient]++;
         } else {
             fo += (int64_t)npf * (1 + dim);
+            T.toff[F] = to;   // one side: the element's own (u, g)
+            to += 2 * (int64_t)npf;
             T.eface[(size_t)r.eL * nlf + r.fL] = {(int)F, 2 | (nF << 5)};
             T.n_boundary++;
             T.n_bnd_trace_points += npf;
