@@ -97,6 +97,23 @@ __device__ __forceinline__ ctab<R> as_const(const R *p) {
     return (ctab<R>)p;
 }
 
+// LDS copy of the interpolation matrices I(n, m) [m][n] for m = n+1 .. 8,
+// the finer traces an element of order p can meet, concatenated by m.
+template <int P>
+struct ITab {
+    static constexpr int N = P + 2;
+    static constexpr int SIZE = N < 8 ? N * ((8 * 9) / 2 - (N * (N + 1)) / 2) : 0;
+};
+template <int P>
+__device__ __forceinline__ int itab_off(int m) {
+    constexpr int N = P + 2;
+    return N * (((m - 1) * m) / 2 - (N * (N + 1)) / 2);
+}
+template <int P>
+__host__ __device__ constexpr int lds_total() {
+    return Sz<P>::TOTAL + ((ITab<P>::SIZE + 3) & ~3);
+}
+
 template <int P>
 __device__ __forceinline__ int pa(int i0, int i1, int i2) {
     return i0 + Sz<P>::S1 * i1 + Sz<P>::S2 * i2;
@@ -264,17 +281,12 @@ __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &
 // trace has the element's points, else interpolated with I (n_F x n) along
 // both face directions through LDS.
 template <class R, int P>
-__device__ __forceinline__ void own_trace(const Data<R> &D, int nf, R *sm, R &u, R &dk, R &da, R &db) {
+__device__ __forceinline__ void own_trace(const R *itl, int nf, R *sm, R &u, R &dk, R &da, R &db) {
     constexpr int N = P + 2;
     if (nf == N) return;
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
     R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
-    const R *__restrict__ I = D.tab + tab_off_I(N, nf);  // [nf][N]
-    // table rows of the first contraction first, so that their loads overlap
-    // the LDS exchange
-    R w1[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) w1[j] = t1 < nf ? I[t1 * N + j] : R(0);
+    const R *I = itl + itab_off<P>(nf);  // [nf][N] in LDS
     if (t1 < N && t2 < N) {
         IS[l] = u;
         IS[W + l] = dk;
@@ -286,22 +298,21 @@ __device__ __forceinline__ void own_trace(const Data<R> &D, int nf, R *sm, R &u,
         R c[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int j = 0; j < N; ++j) {
+            const R w = I[t1 * N + j];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w1[j] * IS[f * W + j + 8 * t2];
+            for (int f = 0; f < 4; ++f) c[f] += w * IS[f * W + j + 8 * t2];
         }
 #pragma unroll
         for (int f = 0; f < 4; ++f) IT[f * W + l] = c[f];
     }
-    R w2[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) w2[j] = t2 < nf ? I[t2 * N + j] : R(0);
     __syncthreads();
     R c[4] = {0, 0, 0, 0};
     if (t1 < nf && t2 < nf) {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
+            const R w = I[t2 * N + j];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w2[j] * IT[f * W + t1 + 8 * j];
+            for (int f = 0; f < 4; ++f) c[f] += w * IT[f * W + t1 + 8 * j];
         }
     }
     u = c[0];
@@ -309,6 +320,171 @@ __device__ __forceinline__ void own_trace(const Data<R> &D, int nf, R *sm, R &u,
     da = c[2];
     db = c[3];
     __syncthreads();
+}
+
+// The same for the two faces of one direction at once (scratch: 1024 R at sm).
+template <class R, int P>
+__device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm, R vA[4], R vB[4]) {
+    constexpr int N = P + 2;
+    const bool nA = nfA != N, nB = nfB != N;
+    if (!nA && !nB) return;
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R *ISA = sm, *ITA = sm + 4 * W, *ISB = sm + 8 * W, *ITB = sm + 12 * W;
+    const R *IA = itl + itab_off<P>(nfA), *IB = itl + itab_off<P>(nfB);
+    if (t1 < N && t2 < N) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if (nA) ISA[f * W + l] = vA[f];
+            if (nB) ISB[f * W + l] = vB[f];
+        }
+    }
+    __syncthreads();
+    if (nA && t1 < nfA && t2 < N) {
+        R c[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const R w = IA[t1 * N + j];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * W + j + 8 * t2];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ITA[f * W + l] = c[f];
+    }
+    if (nB && t1 < nfB && t2 < N) {
+        R c[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const R w = IB[t1 * N + j];
+#pragma unroll
+            for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * W + j + 8 * t2];
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ITB[f * W + l] = c[f];
+    }
+    __syncthreads();
+    if (nA) {
+        R c[4] = {0, 0, 0, 0};
+        if (t1 < nfA && t2 < nfA) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const R w = IA[t2 * N + j];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) c[f] += w * ITA[f * W + t1 + 8 * j];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) vA[f] = c[f];
+    }
+    if (nB) {
+        R c[4] = {0, 0, 0, 0};
+        if (t1 < nfB && t2 < nfB) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const R w = IB[t2 * N + j];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) c[f] += w * ITB[f * W + t1 + 8 * j];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) vB[f] = c[f];
+    }
+    __syncthreads();
+}
+
+// Transposed interpolation of the lifted flux of the two faces of one
+// direction back to the element's face points (scratch: 1024 R at sm).
+template <class R, int P>
+__device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R LA[4], R LB[4]) {
+    constexpr int N = P + 2;
+    const bool nA = nfA != N, nB = nfB != N;
+    if (!nA && !nB) return;
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R *ITA = sm, *ISA = sm + 4 * W, *ITB = sm + 8 * W, *ISB = sm + 12 * W;
+    const R *IA = itl + itab_off<P>(nfA), *IB = itl + itab_off<P>(nfB);
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (nA) ITA[f * W + l] = LA[f];
+        if (nB) ITB[f * W + l] = LB[f];
+    }
+    __syncthreads();
+    if (nA && t1 < nfA && t2 < N) {
+        R c[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t < nfA) {
+                const R w = IA[t * N + t2];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) c[f] += w * ITA[f * W + t1 + 8 * t];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ISA[f * W + l] = c[f];
+    }
+    if (nB && t1 < nfB && t2 < N) {
+        R c[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            if (t < nfB) {
+                const R w = IB[t * N + t2];
+#pragma unroll
+                for (int f = 0; f < 4; ++f) c[f] += w * ITB[f * W + t1 + 8 * t];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) ISB[f * W + l] = c[f];
+    }
+    __syncthreads();
+    if (nA) {
+        R c[4] = {0, 0, 0, 0};
+        if (t1 < N && t2 < N) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < nfA) {
+                    const R w = IA[t * N + t1];
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * W + t + 8 * t2];
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) LA[f] = c[f];
+    }
+    if (nB) {
+        R c[4] = {0, 0, 0, 0};
+        if (t1 < N && t2 < N) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (t < nfB) {
+                    const R w = IB[t * N + t1];
+#pragma unroll
+                    for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * W + t + 8 * t2];
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) LB[f] = c[f];
+    }
+    __syncthreads();
+}
+
+// Flux of eq. IP at this lane's trace point from both sides' (u, g) in the
+// trace buffer (apply kernel of the two-stage structure): this side's test
+// terms L = (F_v, F_g C_k, F_g C_a, F_g C_b), not yet lifted.
+template <class R>
+__device__ __forceinline__ void flux_tb(const FaceU<R> &fu, const FaceD<R> &fd, R L[4]) {
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R Fv = 0, Fg = 0;
+    if (t1 < fu.nf && t2 < fu.nf) {
+        const R un = fu.slot == 2 ? -fd.ou : fd.n0;   // mirrored exterior state on the boundary
+        const R gn = fu.slot == 2 ? -fd.og : fd.n1;
+        const R jump = fd.ou - un;
+        Fv = R(-0.5) * (fd.og - gn) + fu.tau * fd.aw * jump;
+        Fg = R(-0.5) * jump;
+    }
+    L[0] = Fv;
+    L[1] = Fg * fd.Ck;
+    L[2] = Fg * fd.Ca;
+    L[3] = Fg * fd.Cb;
 }
 
 // Neighbour's u and g = C_n . grad_xi u_n at this lane's trace point, from its
@@ -380,8 +556,8 @@ __device__ __forceinline__ void nbr_trace(const Data<R> &D, const FaceU<R> &fu, 
 // a, b < n).  Out: L = (F_v, F_g C_k, F_g C_a, F_g C_b) at the same point, the
 // terms that multiply phi and d_k phi, d_a phi, d_b phi.
 template <class R, int P, int MODE>
-__device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R ou,
-                                          R odk, R oda, R odb, R *sm, R L[4]) {
+__device__ __forceinline__ void face_lift(const Data<R> &D, const R *itl, const FaceU<R> &fu, const FaceD<R> &fd,
+                                          R ou, R odk, R oda, R odb, R *sm, R L[4]) {
     constexpr int N = P + 2;
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
     const int nf = fu.nf;
@@ -393,7 +569,7 @@ __device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, 
     } else {
         R dk = odk, da = oda, db = odb;
         u = ou;
-        own_trace<R, P>(D, nf, sm, u, dk, da, db);
+        own_trace<R, P>(itl, nf, sm, u, dk, da, db);
         g = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
     }
     R un, gn;
@@ -419,58 +595,28 @@ __device__ __forceinline__ void face_lift(const Data<R> &D, const FaceU<R> &fu, 
     L[3] = Fg * fd.Cb;
     if (nf != N) {
         // transposed interpolation back to the element's face points
-        R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
-        const R *__restrict__ I = D.tab + tab_off_I(N, nf);
-        R c1[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) c1[t] = (t < nf && t2 < N) ? I[t * N + t2] : R(0);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) IT[f * W + l] = L[f];
-        __syncthreads();
-        if (t1 < nf && t2 < N) {
-            R c[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (t < nf) {
-#pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += c1[t] * IT[f * W + t1 + 8 * t];
-                }
-            }
-#pragma unroll
-            for (int f = 0; f < 4; ++f) IS[f * W + l] = c[f];
-        }
-        R c2[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) c2[t] = (t < nf && t1 < N) ? I[t * N + t1] : R(0);
-        __syncthreads();
-        R c[4] = {0, 0, 0, 0};
-        if (t1 < N && t2 < N) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                if (t < nf) {
-#pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += c2[t] * IS[f * W + t + 8 * t2];
-                }
-            }
-        }
-#pragma unroll
-        for (int f = 0; f < 4; ++f) L[f] = c[f];
-        __syncthreads();
+        R LB[4] = {0, 0, 0, 0};
+        lift2<R, P>(itl, nf, N, sm + IS_OFF, L, LB);
     }
 }
 
-// Trace of one face of this element: (u, g) at the trace points in canonical
-// order, into the trace buffer (this side's slot).
+// Traces of the two faces of one direction: (u, g) at the trace points in
+// canonical order, into the trace buffer (this side's slot).
 template <class R, int P>
-__device__ __forceinline__ void face_store(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R ou, R odk,
-                                           R oda, R odb, R *sm) {
+__device__ __forceinline__ void face_store2(const Data<R> &D, const R *itl, const FaceU<R> &fA,
+                                            const FaceD<R> &dA, R vA[4], const FaceU<R> &fB, const FaceD<R> &dB,
+                                            R vB[4], R *sm) {
     const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    R u = ou, dk = odk, da = oda, db = odb;
-    own_trace<R, P>(D, fu.nf, sm, u, dk, da, db);
-    if (t1 < fu.nf && t2 < fu.nf) {
-        R *__restrict__ tb = D.tbuf + fu.to + tb_side(fu.slot) * 2 * fu.npf + fd.qc;
-        tb[0] = u;
-        tb[fu.npf] = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
+    own_trace2<R, P>(itl, fA.nf, fB.nf, sm, vA, vB);
+    if (t1 < fA.nf && t2 < fA.nf) {
+        R *__restrict__ tb = D.tbuf + fA.to + tb_side(fA.slot) * 2 * fA.npf + dA.qc;
+        tb[0] = vA[0];
+        tb[fA.npf] = dA.Ck * vA[1] + dA.Ca * vA[2] + dA.Cb * vA[3];
+    }
+    if (t1 < fB.nf && t2 < fB.nf) {
+        R *__restrict__ tb = D.tbuf + fB.to + tb_side(fB.slot) * 2 * fB.npf + dB.qc;
+        tb[0] = vB[0];
+        tb[fB.npf] = dB.Ck * vB[1] + dB.Ca * vB[2] + dB.Cb * vB[3];
     }
 }
 
@@ -497,6 +643,13 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
     const ctab<R> Dt = as_const(D.tab) + tab_off_D(N);   // [N][N]
     const int64_t xo = ed.xoff;
     const MetaV<R> meta = load_meta<R, MODE>(A, D, blockIdx.x);
+    // interpolation tables of this order into LDS (read after several syncs)
+    R *itl = SA + S::TOTAL;
+#pragma unroll
+    for (int m = N + 1; m <= 8; ++m) {
+        const R *__restrict__ src = D.tab + tab_off_I(N, m);
+        for (int i = l; i < m * N; i += W) itl[itab_off<P>(m) + i] = src[i];
+    }
     // trace kernel: every face's per-point data in flight from the start
     FaceU<R> tu[MODE == 0 ? 6 : 1];
     FaceD<R> td[MODE == 0 ? 6 : 1];
@@ -646,18 +799,112 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
     __syncthreads();
 
     if (MODE == 0) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            face_store<R, P>(D, tu[4 + s], td[4 + s], z_u[s], z_dk[s], z_da[s], z_db[s], SA);
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            face_store<R, P>(D, tu[s], td[s], x_u[s], x_dk[s], x_da[s], x_db[s], SA);
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-            face_store<R, P>(D, tu[2 + s], td[2 + s], y_u[s], y_dk[s], y_da[s], y_db[s], SA);
+        {
+            R vA[4] = {z_u[0], z_dk[0], z_da[0], z_db[0]}, vB[4] = {z_u[1], z_dk[1], z_da[1], z_db[1]};
+            face_store2<R, P>(D, itl, tu[4], td[4], vA, tu[5], td[5], vB, SA);
+        }
+        {
+            R vA[4] = {x_u[0], x_dk[0], x_da[0], x_db[0]}, vB[4] = {x_u[1], x_dk[1], x_da[1], x_db[1]};
+            face_store2<R, P>(D, itl, tu[0], td[0], vA, tu[1], td[1], vB, SA);
+        }
+        {
+            R vA[4] = {y_u[0], y_dk[0], y_da[0], y_db[0]}, vB[4] = {y_u[1], y_dk[1], y_da[1], y_db[1]};
+            face_store2<R, P>(D, itl, tu[2], td[2], vA, tu[3], td[3], vB, SA);
+        }
         return;
     }
 
+    if constexpr (MODE == 1) {
+    // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
+    // in chunks, so that the factor loads of one chunk are in flight together
+    if (col) {
+        const R *__restrict__ vg = D.vgeo + ed.voff;
+        const R lam = D.lam[e];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const int p = a + N * (b + N * q);
+            const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
+            const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
+            const R wj = vg[6 * NPTS + p];
+            const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
+            u[q] = lam * wj * u[q];
+            d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
+            d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
+            d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
+            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+        // faces, both of one direction at a time: flux from the trace buffer,
+        // lifted back to the face points, added to the pointwise terms.
+        // Normal to xi_0: own points (q1, q2) on column lanes q0 = 0, n-1.
+        {
+            R LA[4], LB[4];
+            flux_tb<R>(fu0, fd0, LA);
+            flux_tb<R>(fu1, fd1, LB);
+            const FaceU<R> fu2 = face_uniform<R>(meta, 2);
+            const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
+            const FaceU<R> fu3 = face_uniform<R>(meta, 3);
+            const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
+            lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 512, LA, LB);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                FB[f * W + l] = LA[f];
+                FB[4 * W + f * W + l] = LB[f];
+            }
+            __syncthreads();
+            if (col && (a == 0 || a == N - 1)) {
+                const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    u[q] += fb[8 * q];
+                    d0[q] += fb[W + 8 * q];
+                    d1[q] += fb[2 * W + 8 * q];
+                    d2[q] += fb[3 * W + 8 * q];
+                }
+            }
+            __syncthreads();
+            // normal to xi_1: own points (q0, q2) on column lanes q1 = 0, n-1
+            flux_tb<R>(fu2, fd2, LA);
+            flux_tb<R>(fu3, fd3, LB);
+            fu0 = face_uniform<R>(meta, 4);
+            fd0 = load_face<R, MODE>(D, fu0, 2);
+            fu1 = face_uniform<R>(meta, 5);
+            fd1 = load_face<R, MODE>(D, fu1, 2);
+            lift2<R, P>(itl, fu2.nf, fu3.nf, SA + 512, LA, LB);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                FB[f * W + l] = LA[f];
+                FB[4 * W + f * W + l] = LB[f];
+            }
+            __syncthreads();
+            if (col && (b == 0 || b == N - 1)) {
+                const R *fb = FB + (b == 0 ? 0 : 4 * W) + a;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    u[q] += fb[8 * q];
+                    d1[q] += fb[W + 8 * q];
+                    d0[q] += fb[2 * W + 8 * q];
+                    d2[q] += fb[3 * W + 8 * q];
+                }
+            }
+            __syncthreads();
+            // normal to xi_2: own points (q0, q1) are the column ends
+            flux_tb<R>(fu0, fd0, LA);
+            flux_tb<R>(fu1, fd1, LB);
+            lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 512, LA, LB);
+            if (col) {
+                u[0] += LA[0];
+                d2[0] += LA[1];
+                d0[0] += LA[2];
+                d1[0] += LA[3];
+                u[N - 1] += LB[0];
+                d2[N - 1] += LB[1];
+                d0[N - 1] += LB[2];
+                d1[N - 1] += LB[3];
+            }
+        }
+    } else {
     // faces normal to xi_0 and xi_1 first (their own values sit on line lanes);
     // the lifted flux waits in FB until the pointwise terms exist.  The next
     // face's per-point data is always in flight while one face is processed.
@@ -665,20 +912,20 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
         R L[4];
         const FaceU<R> fu2 = face_uniform<R>(meta, 2);
         const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
-        face_lift<R, P, MODE>(D, fu0, fd0, x_u[0], x_dk[0], x_da[0], x_db[0], SA, L);
+        face_lift<R, P, MODE>(D, itl, fu0, fd0, x_u[0], x_dk[0], x_da[0], x_db[0], SA, L);
 #pragma unroll
         for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
         const FaceU<R> fu3 = face_uniform<R>(meta, 3);
         const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
-        face_lift<R, P, MODE>(D, fu1, fd1, x_u[1], x_dk[1], x_da[1], x_db[1], SA, L);
+        face_lift<R, P, MODE>(D, itl, fu1, fd1, x_u[1], x_dk[1], x_da[1], x_db[1], SA, L);
 #pragma unroll
         for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
         fu0 = face_uniform<R>(meta, 4);
         fd0 = load_face<R, MODE>(D, fu0, 2);
-        face_lift<R, P, MODE>(D, fu2, fd2, y_u[0], y_dk[0], y_da[0], y_db[0], SA, L);
+        face_lift<R, P, MODE>(D, itl, fu2, fd2, y_u[0], y_dk[0], y_da[0], y_db[0], SA, L);
 #pragma unroll
         for (int f = 0; f < 4; ++f) FB[512 + f * W + l] = L[f];
-        face_lift<R, P, MODE>(D, fu3, fd3, y_u[1], y_dk[1], y_da[1], y_db[1], SA, L);
+        face_lift<R, P, MODE>(D, itl, fu3, fd3, y_u[1], y_dk[1], y_da[1], y_db[1], SA, L);
 #pragma unroll
         for (int f = 0; f < 4; ++f) FB[512 + 4 * W + f * W + l] = L[f];
     }
@@ -710,14 +957,14 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
         R L[4];
         const FaceU<R> fu5 = face_uniform<R>(meta, 5);
         const FaceD<R> fd5 = load_face<R, MODE>(D, fu5, 2);
-        face_lift<R, P, MODE>(D, fu4, fd4, z_u[0], z_dk[0], z_da[0], z_db[0], SA, L);
+        face_lift<R, P, MODE>(D, itl, fu4, fd4, z_u[0], z_dk[0], z_da[0], z_db[0], SA, L);
         if (col) {
             u[0] += L[0];
             d2[0] += L[1];
             d0[0] += L[2];
             d1[0] += L[3];
         }
-        face_lift<R, P, MODE>(D, fu5, fd5, z_u[1], z_dk[1], z_da[1], z_db[1], SA, L);
+        face_lift<R, P, MODE>(D, itl, fu5, fd5, z_u[1], z_dk[1], z_da[1], z_db[1], SA, L);
         if (col) {
             u[N - 1] += L[0];
             d2[N - 1] += L[1];
@@ -749,6 +996,8 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
         }
     }
     __syncthreads();
+
+    }
 
     // IProduct: y = B^T (m + D_0^T q_0 + D_1^T q_1 + D_2^T q_2)
     R z[N];
