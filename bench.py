@@ -6,8 +6,9 @@ U{3..6} (seeded), lambda = 10, Legendre modes, GLL p+2 points per direction.
 A step is one FP64 operator application y = A x (both kernel stages) on
 seeded N(0,1) coefficients already resident in HBM.  value = N_dof / time
 (GDOF/s).  The same line reports the FP32 application, the per-stage kernel
-times, the HBM roofline of one application (algorithmic bytes / measured
-time), the Jacobi-PCG time to a 1e-10 relative residual in FP64 and as FP32
+times, the HBM roofline of the dominant kernel launch (the algorithmic bytes
+of its elements / its duration from HIP events around each launch) and of
+the whole application, the Jacobi-PCG time to a 1e-10 relative residual in FP64 and as FP32
 inner solves inside FP64 iterative refinement (manufactured solution
 sin(pi x) sin(pi y) sin(pi z)), and the CPU oracle timed on a bounded sample
 of the same workload.
@@ -80,6 +81,20 @@ def source_hash():
             h.update(f.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def kernel_name(variant, order, stage=2):
+    """Kernel symbol (as rocprofv3 prints it, FP64) of one launch."""
+    if variant == "gather_fold":
+        return "sipdg::g3::k3g<double, %d, %d>" % (order, 0 if stage == 1 else 1)
+    if variant == "gather_fold_fused":
+        return "sipdg::g3::k3g<double, %d, 2>" % order
+    if variant == "two_stage":
+        return ("sipdg::f3::k3_trace<double, %d>" % order if stage == 1
+                else "sipdg::f3::k3_apply<double, %d, false>" % order)
+    if variant == "fused":
+        return "sipdg::f3::k3_apply<double, %d, true>" % order
+    return "sipdg::k_%s<double, 3, %d>" % ("trace" if stage == 1 else "apply", order)
 
 
 def time_events(fn, n, stream):
@@ -177,19 +192,26 @@ def main():
     ms_s1 = time_events(lambda: op.apply_stage(x, 1), args.steps, stream)
     ms_s2 = time_events(lambda: op.apply_stage(x, 2, out=y), args.steps, stream)
 
+    # per-launch durations of one application, HIP events around every launch
+    launches = op.apply_timed(x, y, reps=max(10, min(args.steps, 100)), stream=stream)
+
     ndof = op.n_dofs
     b64 = algorithmic_bytes(st, 3, 8)
     b32 = algorithmic_bytes(st, 3, 4)
     flops = algorithmic_flops(mesh, st)
     achieved = b64 / (ms * 1e-3) / 1e9
-    traffic = None
+    apply_launches = [L for L in launches if L["stage"] == 2]
+    dom = max(apply_launches, key=lambda L: L["ms"])
+    dom_name = kernel_name(op.variant, dom["order"])
+    traffic = traffic_app = None
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
             if tr.get("source_hash") == source_hash() and tr.get("variant") == op.variant:
-                traffic = tr.get("bytes_per_apply")
+                traffic_app = tr.get("bytes_per_apply")
+                traffic = tr.get("bytes_per_dispatch", {}).get(dom_name)
         except (OSError, ValueError):
-            traffic = None
+            traffic = traffic_app = None
     out = {
         "metric": METRIC,
         "value": ndof / (ms * 1e-3) / 1e9,
@@ -211,11 +233,24 @@ def main():
             "n_nonconforming_faces": st["n_nonconforming_faces"],
         },
         "roofline": {
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "one application, all order groups (kernel structure: %s)" % op.variant,
-            "algorithmic_bytes": b64,
+            "bound": "hbm", "achieved": dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": dom["alg_bytes"] / (dom["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": dom_name,
+            "launch_ms": dom["ms"], "elements": dom["elements"], "algorithmic_bytes": dom["alg_bytes"],
+            "unit_bytes": "per element of order p: 8*(2(p+1)^3 + 7(p+2)^3 + 1) plus its share of its faces' "
+                          "factors (boundary: 4 n_F^2 values + 32 B; interior: half of 7 n_F^2 values + 32 B)",
         },
+        "roofline_application": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_app, "algorithmic_bytes": b64,
+            "kernels": "all launches of one application (kernel structure: %s)" % op.variant,
+        },
+        "launches": [{"kernel": kernel_name(op.variant, L["order"], L["stage"]), "ms": L["ms"],
+                      "elements": L["elements"],
+                      "gbs": (L["alg_bytes"] / (L["ms"] * 1e-3) / 1e9) if L["alg_bytes"] else None}
+                     for L in launches],
+        "check_algorithmic_bytes": sum(L["alg_bytes"] for L in apply_launches),
         "fp32_apply": {
             "value": ndof / (ms32 * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms32,
             "roofline_frac": b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -132,6 +132,32 @@ int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *str
 int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int stage,
                       void *stream);
 
+/* Measurement: run `reps` applications y = A x back to back with a HIP event
+ * recorded around every kernel launch on the stream, then return per launch
+ * of one application (at most max_launches, in launch order; *n_launches
+ * receives the count):
+ *   ms        mean duration over the reps,
+ *   stage     1 (trace kernels) or 2 (apply kernels),
+ *   order     the polynomial order of the launch's element group,
+ *   elements  the elements it processes,
+ *   alg_bytes the algorithmic bytes of those elements at this precision
+ *             (stage 2 only, 0 for stage 1): each element's coefficients in
+ *             and out, its volume factors and lambda, all of its boundary
+ *             faces' factors and half of its interior faces' factors (7 values
+ *             per trace point: a and both sides' C), plus 32 bytes of
+ *             connectivity per face shared the same way; summed over all
+ *             elements this is the algorithmic traffic of one application.
+ * x, y device; info host.  Synchronous. */
+typedef struct {
+    double ms;
+    int stage;
+    int order;
+    int64_t elements;
+    double alg_bytes;
+} sipdg_launch_info;
+int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int reps,
+                      sipdg_launch_info *info, int max_launches, int *n_launches, void *stream);
+
 /* Kernel structure of sipdg_apply (same results to rounding):
  *   GATHER:    trace values gathered from the element's quadrature points and
  *              interpolated to the trace (Sec. 3.2 GathrInterp), lifted by the
@@ -209,7 +235,9 @@ typedef struct {
     double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 per problem (1e-10) */
     int maxit;         /* max total (inner) iterations, per solve */
     int mode;          /* SIPDG_CG_F64 or SIPDG_CG_F32_IR */
-    double inner_tol;  /* F32_IR: inner relative tolerance (1e-4) */
+    double inner_tol;  /* F32_IR: smallest relative reduction one inner FP32 solve is
+                          asked for (1e-4); each inner solve asks for what the outer
+                          residual still needs, max(inner_tol, tol ||b|| / (2 ||r||)) */
     int precond;       /* 1 = Jacobi, 0 = none */
     int graph_k;       /* iterations per captured HIP graph / per host check; 0 = no graph */
     int max_outer;     /* F32_IR: max refinement steps (50) */

@@ -89,6 +89,16 @@ class CgInfo(ctypes.Structure):
     ]
 
 
+class LaunchInfo(ctypes.Structure):
+    _fields_ = [
+        ("ms", ctypes.c_double),
+        ("stage", ctypes.c_int),
+        ("order", ctypes.c_int),
+        ("elements", ctypes.c_int64),
+        ("alg_bytes", ctypes.c_double),
+    ]
+
+
 # name -> (restype, argtypes)
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 SIGNATURES = {
@@ -104,6 +114,7 @@ SIGNATURES = {
     "sipdg_apply": (_i, [_vp, _vp, _vp, _i, _vp]),
     "sipdg_apply_transpose": (_i, [_vp, _vp, _vp, _i, _vp]),
     "sipdg_apply_stage": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
+    "sipdg_apply_timed": (_i, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(LaunchInfo), _i, ctypes.POINTER(_i), _vp]),
     "sipdg_diagonal": (_i, [_vp, _vp, _vp]),
     "sipdg_param_grad": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "sipdg_set_lambda": (_i, [_vp, _vp, _vp]),

@@ -116,21 +116,35 @@ static void fast_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *t
 template <class R>
 hipError_t launch_gfold3d(int P, int mode, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 
+static inline void rec_mark(LaunchRec *rec, int stage, int gi, bool after, hipStream_t st) {
+    if (!rec || rec->n >= rec->cap) return;
+    (void)hipEventRecord(rec->ev[2 * rec->n + (after ? 1 : 0)], st);
+    if (after) {
+        rec->stage[rec->n] = stage;
+        rec->group[rec->n] = gi;
+        rec->n++;
+    }
+}
+
 template <class R>
-int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages) {
+int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
+               LaunchRec *rec) {
     if (c->variant == SIPDG_VARIANT_GATHER_FOLD || c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED) {
         const bool fused = c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED;
         for (int stage = 1; stage <= 2; ++stage) {
             if (!(stages & stage) || (fused && stage == 1)) continue;
             const int mode = stage == 1 ? 0 : (fused ? 2 : 1);
-            for (const Group &g : c->groups) {
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
                 f3::Args3 A3;
                 f3::Data3<R> D3;
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
                 g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, g.d_desc, g.d_fdesc};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                rec_mark(rec, stage, (int)gi, false, st);
                 hipError_t e = launch_gfold3d<R>(g.P, mode, A, D, st);
+                rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
                     return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
                                                 hipGetErrorString(e));
@@ -141,43 +155,57 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
     if (c->variant != SIPDG_VARIANT_GATHER) {
         const bool fused = c->variant == SIPDG_VARIANT_FUSED;
         if ((stages & 1) && !fused) {
-            for (const Group &g : c->groups) {
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
                 f3::Args3 A;
                 f3::Data3<R> D;
                 fast_args<R>(c, g, x, y, tbuf, skip, false, A, D);
+                rec_mark(rec, 1, (int)gi, false, st);
                 hipError_t e = launch_fast3d<R>(g.P, 0, A, D, st);
+                rec_mark(rec, 1, (int)gi, true, st);
                 if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
             }
         }
         if (stages & 2) {
-            for (const Group &g : c->groups) {
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
                 f3::Args3 A;
                 f3::Data3<R> D;
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A, D);
+                rec_mark(rec, 2, (int)gi, false, st);
                 hipError_t e = launch_fast3d<R>(g.P, fused ? 2 : 1, A, D, st);
+                rec_mark(rec, 2, (int)gi, true, st);
                 if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("apply kernel: ") + hipGetErrorString(e));
             }
         }
         return SIPDG_OK;
     }
     if (stages & 1) {
-        for (const Group &g : c->groups) {
+        for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+            const Group &g = c->groups[gi];
             OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+            rec_mark(rec, 1, (int)gi, false, st);
             hipError_t e = launch_op<R>(c->dim, g.P, OP_TRACE, A, g.nfmax, st);
+            rec_mark(rec, 1, (int)gi, true, st);
             if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
         }
     }
     if (stages & 2) {
-        for (const Group &g : c->groups) {
+        for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+            const Group &g = c->groups[gi];
             OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+            rec_mark(rec, 2, (int)gi, false, st);
             hipError_t e = launch_op<R>(c->dim, g.P, OP_APPLY, A, g.nfmax, st);
+            rec_mark(rec, 2, (int)gi, true, st);
             if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("apply kernel: ") + hipGetErrorString(e));
         }
     }
     return SIPDG_OK;
 }
-template int apply_impl<double>(sipdg_ctx *, const double *, double *, double *, const int *, hipStream_t, int);
-template int apply_impl<float>(sipdg_ctx *, const float *, float *, float *, const int *, hipStream_t, int);
+template int apply_impl<double>(sipdg_ctx *, const double *, double *, double *, const int *, hipStream_t, int,
+                                LaunchRec *);
+template int apply_impl<float>(sipdg_ctx *, const float *, float *, float *, const int *, hipStream_t, int,
+                               LaunchRec *);
 
 int refresh_diag(sipdg_ctx *c, hipStream_t st) {
     hipError_t e = launch_diag(c->dim, c->ne, c->d_order, c->d_xoff, c->d_voff, c->d_eface, c->d_foff,
@@ -341,6 +369,26 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         g.nfmax = nfmax;
         g.d_elems = nullptr;
         TRY(upload(&g.d_elems, ids));
+        {
+            const int d = T.dim, nlf = 2 * d;
+            const int npts = d == 3 ? (P + 2) * (P + 2) * (P + 2) : (P + 2) * (P + 2);
+            const int nm = d == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1);
+            for (int w = 0; w < 2; ++w) {
+                const double wb = w == 0 ? 8.0 : 4.0;
+                double sum = 0;
+                for (int e : ids) {
+                    sum += wb * (2.0 * nm + npts * (d * (d + 1) / 2 + 1) + 1);
+                    for (int f = 0; f < nlf; ++f) {
+                        const FaceRef fr = T.eface[(size_t)e * nlf + f];
+                        const int nf = face_nf(fr.info);
+                        const double npf = d == 3 ? nf * nf : nf;
+                        if (face_slot(fr.info) == 2) sum += wb * (d + 1) * npf + 32.0;
+                        else sum += 0.5 * (wb * (2 * d + 1) * npf + 32.0);
+                    }
+                }
+                g.alg_bytes[w] = sum;
+            }
+        }
         c->groups.push_back(g);
         if (T.dim == 3) {
             std::vector<ElemDesc> desc(ids.size());
@@ -486,6 +534,57 @@ int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int
     if (precision == SIPDG_F32)
         return apply_impl<float>(h, (const float *)x, (float *)y, (float *)h->d_tbuf, nullptr, st, stage);
     return fail(SIPDG_EINVAL, "precision must be SIPDG_F64 or SIPDG_F32");
+}
+
+int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int reps,
+                      sipdg_launch_info *info, int max_launches, int *n_launches, void *stream) {
+    if (!h || !x || !y || !info || !n_launches) return fail(SIPDG_EINVAL, "null argument");
+    if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
+    if (precision != SIPDG_F64 && precision != SIPDG_F32)
+        return fail(SIPDG_EINVAL, "precision must be SIPDG_F64 or SIPDG_F32");
+    if (reps <= 0) reps = 1;
+    hipStream_t st = (hipStream_t)stream;
+    const int per = 2 * (int)h->groups.size();     // launches of one application, at most
+    if (per > 64) return fail(SIPDG_EINVAL, "too many order groups");
+    std::vector<hipEvent_t> ev((size_t)2 * per * reps, nullptr);
+    int rc = SIPDG_OK;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = fail(SIPDG_EHIP, "event create");
+    std::vector<LaunchRec> recs(reps);
+    for (int r = 0; r < reps && rc == SIPDG_OK; ++r) {
+        recs[r].ev = ev.data() + (size_t)2 * per * r;
+        recs[r].cap = per;
+        rc = precision == SIPDG_F64
+                 ? apply_impl<double>(h, (const double *)x, (double *)y, h->d_tbuf, nullptr, st, 3, &recs[r])
+                 : apply_impl<float>(h, (const float *)x, (float *)y, (float *)h->d_tbuf, nullptr, st, 3,
+                                     &recs[r]);
+    }
+    if (rc == SIPDG_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(SIPDG_EHIP, "stream sync");
+    int n = 0;
+    if (rc == SIPDG_OK) {
+        n = std::min(recs[0].n, max_launches);
+        for (int i = 0; i < n; ++i) {
+            double sum = 0;
+            for (int r = 0; r < reps; ++r) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, recs[r].ev[2 * i], recs[r].ev[2 * i + 1]) != hipSuccess) {
+                    rc = fail(SIPDG_EHIP, "event elapsed time");
+                    break;
+                }
+                sum += ms;
+            }
+            const Group &g = h->groups[recs[0].group[i]];
+            info[i].ms = sum / reps;
+            info[i].stage = recs[0].stage[i];
+            info[i].order = g.P;
+            info[i].elements = g.count;
+            info[i].alg_bytes = info[i].stage == 2 ? g.alg_bytes[precision == SIPDG_F64 ? 0 : 1] : 0.0;
+        }
+    }
+    *n_launches = n;
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return rc;
 }
 
 int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision, void *stream) {

@@ -25,7 +25,8 @@ template <class R>
 OpArgs<R> make_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *tbuf, const int *skip);
 
 template <class R>
-int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages = 3);
+int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages = 3,
+               LaunchRec *rec = nullptr);
 
 int refresh_diag(sipdg_ctx *c, hipStream_t st);
 void free_cg(sipdg_ctx *c);

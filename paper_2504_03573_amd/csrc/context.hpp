@@ -75,6 +75,14 @@ struct Group {
     int *d_elems;
     ElemDesc *d_desc = nullptr;      // [count]      (3-D)
     FaceDesc *d_fdesc = nullptr;     // [count][6]   (3-D)
+    double alg_bytes[2] = {0, 0};    // algorithmic bytes of the group's elements (FP64, FP32)
+};
+
+// Optional record of HIP events around each kernel launch of an application.
+struct LaunchRec {
+    hipEvent_t *ev = nullptr;   // [2 * cap]
+    int cap = 0, n = 0;
+    int stage[64], group[64];
 };
 
 struct CgWork;  // defined in the solver

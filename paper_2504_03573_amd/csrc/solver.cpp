@@ -39,7 +39,6 @@ struct CgWork {
     int *d_preconv = nullptr;
     hipGraphExec_t g64 = nullptr, g32 = nullptr;
     int gk64 = 0, gk32 = 0;
-    double gtol64 = -1.0, gtol32 = -1.0;
     int gpre64 = -1, gpre32 = -1;   // preconditioner flag the graph was captured with
 };
 
@@ -97,13 +96,14 @@ static int ensure_cg(sipdg_ctx *c) {
     w->V.prob_blk = w->d_prob_blk;
     w->V.done = w->d_done;
     const int np = c->nprob;
-    ALLOC(w->d_sc, 5 * np);
+    ALLOC(w->d_sc, 5 * np + 1);
     ALLOC(w->d_si, 2 * np + 2);
     w->S.rho = w->d_sc;
     w->S.alpha = w->d_sc + np;
     w->S.beta = w->d_sc + 2 * np;
     w->S.bnorm = w->d_sc + 3 * np;
     w->S.rel = w->d_sc + 4 * np;
+    w->S.tol = w->d_sc + 5 * np;
     w->S.conv = w->d_si;
     w->S.iters = w->d_si + np;
     w->S.counter = w->d_si + 2 * np;
@@ -136,7 +136,7 @@ static int ensure_cg32(sipdg_ctx *c) {
 
 // One CG iteration in precision R on the work vectors.
 template <class R>
-static int cg_body(sipdg_ctx *c, double tol, bool precond) {
+static int cg_body(sipdg_ctx *c, bool precond) {
     CgWork *w = c->cg;
     hipStream_t st = w->stream;
     R *x, *r, *z, *p, *q;
@@ -153,7 +153,7 @@ static int cg_body(sipdg_ctx *c, double tol, bool precond) {
     HIPCHK(vec_dot<R>(w->V, p, q, w->p1, st));
     HIPCHK(vec_fin_alpha(w->V, w->S, w->p1, st));
     HIPCHK(vec_update<R>(w->V, w->S, x, r, p, q, dinv, z, w->p1, w->p2, st));
-    HIPCHK(vec_fin_beta(w->V, w->S, w->p1, w->p2, tol, st));
+    HIPCHK(vec_fin_beta(w->V, w->S, w->p1, w->p2, st));
     HIPCHK(vec_pupdate<R>(w->V, w->S, z, p, st));
     return SIPDG_OK;
 }
@@ -170,10 +170,9 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
     all_done = 0;
     hipGraphExec_t *gexec = sizeof(R) == 8 ? &w->g64 : &w->g32;
     int *gk = sizeof(R) == 8 ? &w->gk64 : &w->gk32;
-    double *gtol = sizeof(R) == 8 ? &w->gtol64 : &w->gtol32;
     int *gpre = sizeof(R) == 8 ? &w->gpre64 : &w->gpre32;
     const int pre = o.precond != 0;
-    if (o.graph_k > 0 && maxit >= k && (*gexec == nullptr || *gk != k || *gtol != tol || *gpre != pre)) {
+    if (o.graph_k > 0 && maxit >= k && (*gexec == nullptr || *gk != k || *gpre != pre)) {
         if (*gexec) {
             (void)hipGraphExecDestroy(*gexec);
             *gexec = nullptr;
@@ -181,7 +180,7 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
         hipGraph_t graph;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         int rc = SIPDG_OK;
-        for (int i = 0; i < k && rc == SIPDG_OK; ++i) rc = cg_body<R>(c, tol, o.precond != 0);
+        for (int i = 0; i < k && rc == SIPDG_OK; ++i) rc = cg_body<R>(c, o.precond != 0);
         hipError_t ec = hipStreamEndCapture(st, &graph);
         if (rc) {
             if (ec == hipSuccess) (void)hipGraphDestroy(graph);
@@ -192,7 +191,6 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
         (void)hipGraphDestroy(graph);
         HIPCHK(ei);
         *gk = k;
-        *gtol = tol;
         *gpre = pre;
     }
     int last_ckpt = 0;
@@ -204,7 +202,7 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
             HIPCHK(hipGraphLaunch(*gexec, st));
         } else {
             for (int i = 0; i < std::min(k, remaining); ++i) {
-                int rc = cg_body<R>(c, tol, o.precond != 0);
+                int rc = cg_body<R>(c, o.precond != 0);
                 if (rc) return rc;
             }
         }
@@ -331,13 +329,21 @@ int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_op
             }
             if (o.checkpoint && o.checkpoint_every > 0) o.checkpoint(o.checkpoint_user, w->x64, w->r64, total_iters);
             if (all || outer >= o.max_outer || total_iters >= o.maxit || breakdown) break;
+            // the inner solve asks for the reduction the outer residual still
+            // needs (half of it, for the FP32 solve's own error), but never for
+            // less than inner_tol: the last refinement does no more work than
+            // required
+            double itol = 1.0;
+            for (int p = 0; p < h->nprob; ++p)
+                if (!preconv[p] && nr[p] > 0.0) itol = std::min(itol, 0.5 * o.tol * bn[p] / nr[p]);
+            itol = std::min(std::max(itol, o.inner_tol), 0.5);
             HIPCHK(hipMemcpyAsync(w->d_preconv, preconv.data(), sizeof(int) * h->nprob, hipMemcpyHostToDevice, st));
             HIPCHK(vec_scale32(w->V, w->r64, w->d_norm, w->r32, st));
             HIPCHK(vec_start<float>(w->V, w->r32, o.precond ? h->d_dinv32 : nullptr, w->z32, w->pp32,
                                     w->x32, w->p1, w->p2, st));
-            HIPCHK(vec_fin_start(w->V, w->S, w->p1, w->p2, nullptr, w->d_preconv, o.inner_tol, st));
+            HIPCHK(vec_fin_start(w->V, w->S, w->p1, w->p2, nullptr, w->d_preconv, itol, st));
             int it = 0, idone = 0;
-            rc = cg_loop<float>(h, o, o.inner_tol, o.maxit - total_iters, it, flags, idone, false, total_iters);
+            rc = cg_loop<float>(h, o, itol, o.maxit - total_iters, it, flags, idone, false, total_iters);
             if (rc) return rc;
             total_iters += it;
             breakdown = (flags & 2) != 0;

@@ -27,6 +27,7 @@ struct CgScalars {
     int *iters;     // iterations per problem
     int *counter;   // [1] iterations executed by the whole batch
     int *flags;     // [1] bit 1: breakdown seen
+    double *tol;    // [1] relative tolerance of the running solve (set by the start kernel)
 };
 
 template <class R>
@@ -43,7 +44,7 @@ template <class R>
 hipError_t vec_fill(R *v, int64_t n, R val, hipStream_t st);
 hipError_t vec_fin_alpha(const VecCtx &V, const CgScalars &S, const double *ppq, hipStream_t st);
 hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
-                        double tol, hipStream_t st);
+                        hipStream_t st);
 hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
                          const double *bnorm_src, const int *preconv, double tol, hipStream_t st);
 hipError_t vec_fin_norm(const VecCtx &V, const double *part, double *out, hipStream_t st);

@@ -90,8 +90,9 @@ __global__ void k_fin_alpha(VecCtx V, CgScalars S, const double *ppq) {
 }
 
 // residual test and beta per problem; sets *done when every problem stopped.
-__global__ void k_fin_beta(VecCtx V, CgScalars S, const double *prr, const double *prz, double tol) {
+__global__ void k_fin_beta(VecCtx V, CgScalars S, const double *prr, const double *prz) {
     if (V.done && *V.done) return;
+    const double tol = S.tol[0];
     __shared__ int active;
     if (threadIdx.x == 0) active = 0;
     __syncthreads();
@@ -177,6 +178,7 @@ __global__ void k_fin_start(VecCtx V, CgScalars S, const double *prr, const doub
         *V.done = active == 0 ? 1 : 0;
         S.counter[0] = 0;
         S.flags[0] = 0;
+        S.tol[0] = tol;
     }
 }
 
@@ -262,9 +264,8 @@ hipError_t vec_fin_alpha(const VecCtx &V, const CgScalars &S, const double *ppq,
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(64), 0, st, V, S, ppq);
     LCHK();
 }
-hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
-                        double tol, hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(64), 0, st, V, S, prr, prz, tol);
+hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz, hipStream_t st) {
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(64), 0, st, V, S, prr, prz);
     LCHK();
 }
 hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,

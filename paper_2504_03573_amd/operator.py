@@ -146,6 +146,22 @@ class SipdgOperator:
                                             prec, int(stage), _stream_ptr(stream)))
         return out
 
+    def apply_timed(self, x: torch.Tensor, out: torch.Tensor, reps: int = 20, stream=None) -> list[dict]:
+        """Run ``reps`` applications with a HIP event around every kernel
+        launch; per launch of one application: mean ms, stage, order, element
+        count and the algorithmic bytes of its elements (apply launches)."""
+        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        if prec is None:
+            raise TypeError("x must be float64 or float32")
+        self._vec(x, x.dtype, name="x")
+        self._vec(out, x.dtype, name="out")
+        info = (C.LaunchInfo * 64)()
+        n = ctypes.c_int()
+        C.check(self._lib.sipdg_apply_timed(self._h, _ptr(x), _ptr(out), prec, int(reps), info, 64,
+                                            ctypes.byref(n), _stream_ptr(stream)))
+        return [{"ms": info[i].ms, "stage": info[i].stage, "order": info[i].order,
+                 "elements": int(info[i].elements), "alg_bytes": info[i].alg_bytes} for i in range(n.value)]
+
     def apply_transpose(self, g: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(g.dtype)
         if prec is None:

@@ -1,0 +1,54 @@
+"""The per-launch measurement entry point: launch structure, the algorithmic
+byte shares per launch (they must add up to the algorithmic traffic of one
+application) and unchanged results."""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2504_03573_amd as P
+    return P
+
+
+def _alg_bytes(st, dim, word):
+    words = (2 * st["n_dofs"] + st["n_volume_points"] * (dim * (dim + 1) // 2 + 1)
+             + st["n_interior_trace_points"] * (2 * dim + 1) + st["n_boundary_trace_points"] * (dim + 1)
+             + st["n_elems"])
+    return word * words + 32 * (st["n_interior_faces"] + st["n_boundary_faces"])
+
+
+@pytest.mark.parametrize("variant", ["gather_fold", "two_stage", "gather"])
+def test_apply_timed(P, variant):
+    print(f"[apply_timed {variant}]", flush=True)
+    m = synth.workload(3, N=6)
+    st = P.inspect_mesh(m)
+    op = P.SipdgOperator(m)
+    op.variant = variant
+    groups = len(set(m.order.tolist()))
+    x = torch.tensor(synth.random_coefficients(m, 4006), device="cuda")
+    y_ref = op.apply(x)
+    for dt, word in ((torch.float64, 8), (torch.float32, 4)):
+        xx = x.to(dt)
+        y = torch.empty_like(xx)
+        launches = op.apply_timed(xx, y, reps=3)
+        assert len(launches) == 2 * groups
+        assert [L["stage"] for L in launches] == [1] * groups + [2] * groups
+        assert sorted(L["order"] for L in launches[groups:]) == sorted(set(m.order.tolist()))
+        assert sum(L["elements"] for L in launches[groups:]) == m.n_elems
+        assert all(L["ms"] > 0 for L in launches)
+        assert sum(L["alg_bytes"] for L in launches) == pytest.approx(_alg_bytes(st, 3, word), rel=1e-12)
+        if dt == torch.float64:
+            assert torch.equal(y, y_ref)
+        else:
+            assert torch.allclose(y.double(), y_ref, rtol=0, atol=1e-5 * float(y_ref.abs().max()))
