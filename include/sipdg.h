@@ -175,8 +175,10 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
  *              lifted flux is added to the volume's pointwise terms so that
  *              one IProduct lifts faces and volume (Sec. 3.2 GathrInterp;
  *              Sec. 3.3).  A trace kernel stores every interior face side's
- *              (u, g), then the apply kernel reads the neighbour's.  3-D,
- *              orders <= 6.  Default when allowed (GATHER otherwise).
+ *              (u, g), then the apply kernel reads the neighbour's.  3-D;
+ *              an order group above 6, or touching a neighbour above 6, uses
+ *              the GATHER kernels (same trace buffer).  Default in 3-D
+ *              (GATHER in 2-D).
  *   GATHER_FOLD_FUSED: as GATHER_FOLD, but the neighbour's traces are
  *              evaluated from its coefficients (TracePhysEval): one launch
  *              per order group, no trace buffer.  3-D, orders <= 6. */

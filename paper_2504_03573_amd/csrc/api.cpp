@@ -136,6 +136,18 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
             const int mode = stage == 1 ? 0 : (fused ? 2 : 1);
             for (size_t gi = 0; gi < c->groups.size(); ++gi) {
                 const Group &g = c->groups[gi];
+                if (g.P > 6 || g.nfmax > 8) {
+                    // orders above 6, or a neighbour above 6 (a trace finer than the
+                    // 8 x 8 lane grid): the general kernels, same trace-buffer layout
+                    OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+                    rec_mark(rec, stage, (int)gi, false, st);
+                    hipError_t e = launch_op<R>(c->dim, g.P, stage == 1 ? OP_TRACE : OP_APPLY, A, g.nfmax, st);
+                    rec_mark(rec, stage, (int)gi, true, st);
+                    if (e != hipSuccess)
+                        return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
+                                                    hipGetErrorString(e));
+                    continue;
+                }
                 f3::Args3 A3;
                 f3::Data3<R> D3;
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
@@ -420,15 +432,17 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         int pmax = 0;
         for (int o : T.order) pmax = std::max(pmax, o);
         c->fast_ok = T.dim == 3 && pmax <= 6;
-        c->variant = c->fast_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
+        c->gfold_ok = T.dim == 3;
+        c->variant = c->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
         const char *env = std::getenv("SIPDG_VARIANT");
-        if (env && c->fast_ok) {
+        if (env && c->gfold_ok) {
             std::string v(env);
             if (v == "gather") c->variant = SIPDG_VARIANT_GATHER;
             else if (v == "two_stage") c->variant = SIPDG_VARIANT_TWO_STAGE;
             else if (v == "fused") c->variant = SIPDG_VARIANT_FUSED;
             else if (v == "gather_fold") c->variant = SIPDG_VARIANT_GATHER_FOLD;
             else if (v == "gather_fold_fused") c->variant = SIPDG_VARIANT_GATHER_FOLD_FUSED;
+            if (!c->fast_ok && c->variant != SIPDG_VARIANT_GATHER_FOLD) c->variant = SIPDG_VARIANT_GATHER;
         }
     }
     TRY(dalloc(&c->d_diag64, T.ndof));
@@ -680,7 +694,11 @@ int sipdg_set_variant(sipdg_handle h, int variant) {
     }
     if (variant < 0 || variant >= SIPDG_NUM_VARIANTS)
         return fail(SIPDG_EINVAL, "unknown variant");
-    if (!h->fast_ok) return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
+    if (variant == SIPDG_VARIANT_GATHER_FOLD) {
+        if (!h->gfold_ok) return fail(SIPDG_EINVAL, "gather_fold needs a 3-D mesh");
+    } else if (!h->fast_ok) {
+        return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
+    }
     h->variant = variant;
     return SIPDG_OK;
 }
@@ -708,7 +726,7 @@ int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
     int rc = SIPDG_OK;
     for (int v = 0; v < SIPDG_NUM_VARIANTS && rc == SIPDG_OK; ++v) {
         if (ms_out) ms_out[v] = 0.0;
-        if (v != SIPDG_VARIANT_GATHER && !h->fast_ok) continue;
+        if (v == SIPDG_VARIANT_GATHER_FOLD ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)) continue;
         h->variant = v;
         for (int i = 0; i < 3 && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
         if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SIPDG_EHIP, "event record");

@@ -126,4 +126,5 @@ struct sipdg_ctx {
     sipdg::CgWork *cg = nullptr;
     int variant = 0;        // SIPDG_VARIANT_*
     bool fast_ok = false;   // 3-D with every order <= 6
+    bool gfold_ok = false;  // 3-D: gather-fold for order <= 6 groups, general kernels above
 };

@@ -1,5 +1,7 @@
 // Gather-fold hexahedron kernel, orders 1..6 (n = p+2 <= 8 GLL points per
-// direction), one 64-lane wavefront per element, one launch per order group.
+// direction) whose faces all have traces of at most 8 x 8 points (every
+// neighbour of order <= 6), one 64-lane wavefront per element, one launch per
+// order group.
 //
 // Volume terms (Xia & Moxey, Sec. 3.1 basic operators): lane (q0, q1) keeps
 // the xi_2 column of its n points in registers ("column layout").  BwdTrans,
