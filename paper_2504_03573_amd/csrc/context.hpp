@@ -125,6 +125,11 @@ struct sipdg_ctx {
     std::vector<sipdg::Group> groups;
     sipdg::CgWork *cg = nullptr;
     int variant = 0;        // SIPDG_VARIANT_*
+    // side streams (default priority) and events: the order groups of one
+    // stage run concurrently, joined back into the caller's stream
+    std::vector<hipStream_t> gstreams;
+    std::vector<hipEvent_t> gevents;   // [0] fork, [1 + g] group g done
+    bool concurrent = true;
     bool fast_ok = false;   // 3-D with every order <= 6
     bool gfold_ok = false;  // 3-D: gather-fold for order <= 6 groups, general kernels above
 };
