@@ -129,7 +129,7 @@ struct sipdg_ctx {
     // stage run concurrently, joined back into the caller's stream
     std::vector<hipStream_t> gstreams;
     std::vector<hipEvent_t> gevents;   // [0] fork, [1 + g] group g done
-    bool concurrent = true;
+    bool concurrent = false;
     bool fast_ok = false;   // 3-D with every order <= 6
     bool gfold_ok = false;  // 3-D: gather-fold for order <= 6 groups, general kernels above
 };

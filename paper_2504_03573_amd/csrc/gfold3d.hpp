@@ -111,9 +111,22 @@ __device__ __forceinline__ int itab_off(int m) {
     constexpr int N = P + 2;
     return N * (((m - 1) * m) / 2 - (N * (N + 1)) / 2);
 }
+// LDS copy of the trace tables P_i(z_t), P'_i(z_t), i < 7, at the m-point
+// GLL traces m = n .. 8 a face of an element of order p can have (fused
+// kernel: the neighbour's trace evaluation), [m][7] each, BF then DBF per m.
 template <int P>
-__host__ __device__ constexpr int lds_total() {
-    return Sz<P>::TOTAL + ((ITab<P>::SIZE + 3) & ~3);
+struct BTab {
+    static constexpr int N = P + 2;
+    static constexpr int SIZE = N <= 8 ? 14 * ((8 * 9) / 2 - ((N - 1) * N) / 2) : 0;
+};
+template <int P>
+__device__ __forceinline__ int btab_off(int m) {
+    constexpr int N = P + 2;
+    return 14 * (((m - 1) * m) / 2 - ((N - 1) * N) / 2);
+}
+template <int P>
+__host__ __device__ constexpr int lds_total(int mode) {
+    return Sz<P>::TOTAL + ((ITab<P>::SIZE + 3) & ~3) + (mode == 2 ? ((BTab<P>::SIZE + 3) & ~3) : 0);
 }
 
 template <int P>
@@ -553,6 +566,141 @@ __device__ __forceinline__ void nbr_trace(const Data<R> &D, const FaceU<R> &fu, 
     __syncthreads();
 }
 
+// Reduction of the neighbour's coefficients along its face normal with
+// P_i(s), P'_i(s) (first step of TracePhysEval), at lane (ia, ib) of its face
+// modes; zero elsewhere and on boundary faces.
+template <class R>
+__device__ __forceinline__ void nbr_reduce(const Data<R> &D, const FaceU<R> &fu, R &v0, R &v1) {
+    v0 = v1 = R(0);
+    if (fu.slot == 2) return;
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    if (t1 < fu.npn && t2 < fu.npn) {
+        const R *__restrict__ xn = D.x + fu.xn;
+#pragma unroll
+        for (int ik = 0; ik < 7; ++ik) {
+            if (ik < fu.npn) {
+                const R xv = xn[mode_rt(fu.npn, fu.kn, t1, t2, ik)];
+                v0 += end_val<R>(ik, fu.sn) * xv;
+                v1 += end_der<R>(ik, fu.sn) * xv;
+            }
+        }
+    }
+}
+
+// The neighbours' u and g = C_n . grad_xi u_n at this lane's trace point for
+// the two faces of one direction, from their face-normal reductions: the two
+// contractions of TracePhysEval with the LDS trace tables, the second one at
+// the neighbour's coordinates of this lane's point (scratch: 640 R at sm).
+template <class R, int P>
+__device__ __forceinline__ void nbr_pair(const R *btl, const FaceU<R> &fA, const FaceD<R> &dA, R a0, R a1,
+                                         const FaceU<R> &fB, const FaceD<R> &dB, R b0, R b1, R *sm, R &unA,
+                                         R &gnA, R &unB, R &gnB) {
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R *NU = sm, *NWA = sm + 4 * W, *NWB = sm + 7 * W;
+    const bool iA = fA.slot != 2, iB = fB.slot != 2;
+    unA = gnA = unB = gnB = R(0);
+    if (!iA && !iB) return;
+    NU[l] = a0;
+    NU[W + l] = a1;
+    NU[2 * W + l] = b0;
+    NU[3 * W + l] = b1;
+    __syncthreads();
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const FaceU<R> &f = side ? fB : fA;
+        if (side ? !iB : !iA) continue;
+        if (t1 < f.nf && t2 < f.npn) {
+            const R *bf = btl + btab_off<P>(f.nf) + 7 * t1, *dbf = bf + 7 * f.nf;
+            const R *u0 = NU + 2 * side * W + 8 * t2, *u1 = u0 + W;
+            R w0 = 0, w0d = 0, w1 = 0;
+#pragma unroll
+            for (int ia = 0; ia < 7; ++ia) {
+                if (ia < f.npn) {
+                    const R bv = bf[ia], x0 = u0[ia];
+                    w0 += bv * x0;
+                    w0d += dbf[ia] * x0;
+                    w1 += bv * u1[ia];
+                }
+            }
+            R *nw = side ? NWB : NWA;
+            nw[l] = w0;
+            nw[W + l] = w0d;
+            nw[2 * W + l] = w1;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const FaceU<R> &f = side ? fB : fA;
+        const FaceD<R> &d = side ? dB : dA;
+        if (side ? !iB : !iA) continue;
+        if (t1 < f.nf && t2 < f.nf) {
+            int r1, r2;
+            canon_inverse(f.on, f.nf, d.qc, r1, r2);
+            const R *bf = btl + btab_off<P>(f.nf) + 7 * r2, *dbf = bf + 7 * f.nf;
+            const R *nw = (side ? NWB : NWA) + r1;
+            R vu = 0, vda = 0, vdb = 0, vdk = 0;
+#pragma unroll
+            for (int ib = 0; ib < 7; ++ib) {
+                if (ib < f.npn) {
+                    const R bv = bf[ib], w0 = nw[8 * ib];
+                    vu += bv * w0;
+                    vda += bv * nw[W + 8 * ib];
+                    vdb += dbf[ib] * w0;
+                    vdk += bv * nw[2 * W + 8 * ib];
+                }
+            }
+            const R un = vu, gn = d.n0 * vdk + d.n1 * vda + d.n2 * vdb;
+            if (side) {
+                unB = un;
+                gnB = gn;
+            } else {
+                unA = un;
+                gnA = gn;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Flux of eq. IP at this lane's trace point from the element's own (u, g) and
+// the neighbour's (or the mirrored state on the boundary): this side's test
+// terms L = (F_v, F_g C_k, F_g C_a, F_g C_b), not yet lifted.
+template <class R>
+__device__ __forceinline__ void flux_own(const FaceU<R> &fu, const FaceD<R> &fd, R u, R g, R un, R gn, R L[4]) {
+    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    R Fv = 0, Fg = 0;
+    if (t1 < fu.nf && t2 < fu.nf) {
+        if (fu.slot == 2) {
+            un = -u;
+            gn = -g;
+        }
+        const R jump = u - un;
+        Fv = R(-0.5) * (g - gn) + fu.tau * fd.aw * jump;
+        Fg = R(-0.5) * jump;
+    }
+    L[0] = Fv;
+    L[1] = Fg * fd.Ck;
+    L[2] = Fg * fd.Ca;
+    L[3] = Fg * fd.Cb;
+}
+
+// Fused apply, one direction: own traces (interpolated when finer), the
+// neighbours' by TracePhysEval, flux, lift back to the face points.
+template <class R, int P>
+__device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, const FaceU<R> &fA, const FaceD<R> &dA,
+                                                R vA[4], R a0, R a1, const FaceU<R> &fB, const FaceD<R> &dB,
+                                                R vB[4], R b0, R b1, R *sm, R LA[4], R LB[4]) {
+    own_trace2<R, P>(itl, fA.nf, fB.nf, sm, vA, vB);
+    const R gA = dA.Ck * vA[1] + dA.Ca * vA[2] + dA.Cb * vA[3];
+    const R gB = dB.Ck * vB[1] + dB.Ca * vB[2] + dB.Cb * vB[3];
+    R unA, gnA, unB, gnB;
+    nbr_pair<R, P>(btl, fA, dA, a0, a1, fB, dB, b0, b1, sm, unA, gnA, unB, gnB);
+    flux_own<R>(fA, dA, vA[0], gA, unA, gnA, LA);
+    flux_own<R>(fB, dB, vB[0], gB, unB, gnB, LB);
+    lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
+}
+
 // Lift of the flux of one face at this lane's own face point.  In: the
 // element's u, d_k u, d_a u, d_b u at its face point (a, b) = lane (valid for
 // a, b < n).  Out: L = (F_v, F_g C_k, F_g C_a, F_g C_b) at the same point, the
@@ -651,6 +799,22 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
     for (int m = N + 1; m <= 8; ++m) {
         const R *__restrict__ src = D.tab + tab_off_I(N, m);
         for (int i = l; i < m * N; i += W) itl[itab_off<P>(m) + i] = src[i];
+    }
+    // fused: the trace tables, and every neighbour's face-normal reduction
+    // (their coefficient loads in flight together, during the volume work)
+    R *btl = itl + ((ITab<P>::SIZE + 3) & ~3);
+    R nv0[MODE == 2 ? 6 : 1], nv1[MODE == 2 ? 6 : 1];
+    if (MODE == 2) {
+#pragma unroll
+        for (int m = N; m <= 8; ++m) {
+            const R *__restrict__ bf = D.tab + tab_off_BF(m), *__restrict__ dbf = D.tab + tab_off_DBF(m);
+            for (int i = l; i < 7 * m; i += W) {
+                btl[btab_off<P>(m) + i] = bf[(i / 7) * S9 + i % 7];
+                btl[btab_off<P>(m) + 7 * m + i] = dbf[(i / 7) * S9 + i % 7];
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < (MODE == 2 ? 6 : 0); ++f) nbr_reduce<R>(D, face_uniform<R>(meta, f), nv0[f], nv1[f]);
     }
     // trace kernel: every face's per-point data in flight from the start
     FaceU<R> tu[MODE == 0 ? 6 : 1];
@@ -907,98 +1071,91 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
             }
         }
     } else {
-    // faces normal to xi_0 and xi_1 first (their own values sit on line lanes);
-    // the lifted flux waits in FB until the pointwise terms exist.  The next
-    // face's per-point data is always in flight while one face is processed.
-    {
-        R L[4];
-        const FaceU<R> fu2 = face_uniform<R>(meta, 2);
-        const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
-        face_lift<R, P, MODE>(D, itl, fu0, fd0, x_u[0], x_dk[0], x_da[0], x_db[0], SA, L);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) FB[f * W + l] = L[f];
-        const FaceU<R> fu3 = face_uniform<R>(meta, 3);
-        const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
-        face_lift<R, P, MODE>(D, itl, fu1, fd1, x_u[1], x_dk[1], x_da[1], x_db[1], SA, L);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) FB[4 * W + f * W + l] = L[f];
-        fu0 = face_uniform<R>(meta, 4);
-        fd0 = load_face<R, MODE>(D, fu0, 2);
-        face_lift<R, P, MODE>(D, itl, fu2, fd2, y_u[0], y_dk[0], y_da[0], y_db[0], SA, L);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) FB[512 + f * W + l] = L[f];
-        face_lift<R, P, MODE>(D, itl, fu3, fd3, y_u[1], y_dk[1], y_da[1], y_db[1], SA, L);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) FB[512 + 4 * W + f * W + l] = L[f];
-    }
-    FaceU<R> fu4 = fu0;
-    FaceD<R> fd4 = fd0;
-
-    // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
-    // in chunks, so that the factor loads of one chunk are in flight together
-    if (col) {
-        const R *__restrict__ vg = D.vgeo + ed.voff;
-        const R lam = D.lam[e];
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            const int p = a + N * (b + N * q);
-            const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
-            const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
-            const R wj = vg[6 * NPTS + p];
-            const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
-            u[q] = lam * wj * u[q];
-            d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
-            d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
-            d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
-            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-
-    // faces normal to xi_2: own points are the column ends
-    {
-        R L[4];
-        const FaceU<R> fu5 = face_uniform<R>(meta, 5);
-        const FaceD<R> fd5 = load_face<R, MODE>(D, fu5, 2);
-        face_lift<R, P, MODE>(D, itl, fu4, fd4, z_u[0], z_dk[0], z_da[0], z_db[0], SA, L);
+        // fused: as the two-stage apply, with the element's own traces from its
+        // face values and the neighbours' evaluated here
         if (col) {
-            u[0] += L[0];
-            d2[0] += L[1];
-            d0[0] += L[2];
-            d1[0] += L[3];
-        }
-        face_lift<R, P, MODE>(D, itl, fu5, fd5, z_u[1], z_dk[1], z_da[1], z_db[1], SA, L);
-        if (col) {
-            u[N - 1] += L[0];
-            d2[N - 1] += L[1];
-            d0[N - 1] += L[2];
-            d1[N - 1] += L[3];
-        }
-    }
-    __syncthreads();
-    // lifted flux of the faces normal to xi_0 (column lanes q0 = 0, n-1) and
-    // xi_1 (column lanes q1 = 0, n-1)
-    if (col && (a == 0 || a == N - 1)) {
-        const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
+            const R *__restrict__ vg = D.vgeo + ed.voff;
+            const R lam = D.lam[e];
 #pragma unroll
-        for (int q = 0; q < N; ++q) {
-            u[q] += fb[8 * q];
-            d0[q] += fb[W + 8 * q];
-            d1[q] += fb[2 * W + 8 * q];
-            d2[q] += fb[3 * W + 8 * q];
+            for (int q = 0; q < N; ++q) {
+                const int p = a + N * (b + N * q);
+                const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
+                const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
+                const R wj = vg[6 * NPTS + p];
+                const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
+                u[q] = lam * wj * u[q];
+                d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
+                d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
+                d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
+                if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
         }
-    }
-    if (col && (b == 0 || b == N - 1)) {
-        const R *fb = FB + 512 + (b == 0 ? 0 : 4 * W) + a;
+        R LA[4], LB[4];
+        {
+            const FaceU<R> fu2 = face_uniform<R>(meta, 2);
+            const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
+            const FaceU<R> fu3 = face_uniform<R>(meta, 3);
+            const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
+            R vA[4] = {x_u[0], x_dk[0], x_da[0], x_db[0]}, vB[4] = {x_u[1], x_dk[1], x_da[1], x_db[1]};
+            face_pair_fused<R, P>(itl, btl, fu0, fd0, vA, nv0[0], nv1[0], fu1, fd1, vB, nv0[1], nv1[1], SA + 512,
+                                  LA, LB);
 #pragma unroll
-        for (int q = 0; q < N; ++q) {
-            u[q] += fb[8 * q];
-            d1[q] += fb[W + 8 * q];
-            d0[q] += fb[2 * W + 8 * q];
-            d2[q] += fb[3 * W + 8 * q];
+            for (int f = 0; f < 4; ++f) {
+                FB[f * W + l] = LA[f];
+                FB[4 * W + f * W + l] = LB[f];
+            }
+            __syncthreads();
+            if (col && (a == 0 || a == N - 1)) {
+                const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    u[q] += fb[8 * q];
+                    d0[q] += fb[W + 8 * q];
+                    d1[q] += fb[2 * W + 8 * q];
+                    d2[q] += fb[3 * W + 8 * q];
+                }
+            }
+            __syncthreads();
+            fu0 = face_uniform<R>(meta, 4);
+            fd0 = load_face<R, MODE>(D, fu0, 2);
+            fu1 = face_uniform<R>(meta, 5);
+            fd1 = load_face<R, MODE>(D, fu1, 2);
+            R wA[4] = {y_u[0], y_dk[0], y_da[0], y_db[0]}, wB[4] = {y_u[1], y_dk[1], y_da[1], y_db[1]};
+            face_pair_fused<R, P>(itl, btl, fu2, fd2, wA, nv0[2], nv1[2], fu3, fd3, wB, nv0[3], nv1[3], SA + 512,
+                                  LA, LB);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                FB[f * W + l] = LA[f];
+                FB[4 * W + f * W + l] = LB[f];
+            }
+            __syncthreads();
+            if (col && (b == 0 || b == N - 1)) {
+                const R *fb = FB + (b == 0 ? 0 : 4 * W) + a;
+#pragma unroll
+                for (int q = 0; q < N; ++q) {
+                    u[q] += fb[8 * q];
+                    d1[q] += fb[W + 8 * q];
+                    d0[q] += fb[2 * W + 8 * q];
+                    d2[q] += fb[3 * W + 8 * q];
+                }
+            }
+            __syncthreads();
         }
-    }
-    __syncthreads();
-
+        {
+            R vA[4] = {z_u[0], z_dk[0], z_da[0], z_db[0]}, vB[4] = {z_u[1], z_dk[1], z_da[1], z_db[1]};
+            face_pair_fused<R, P>(itl, btl, fu0, fd0, vA, nv0[4], nv1[4], fu1, fd1, vB, nv0[5], nv1[5], SA + 512,
+                                  LA, LB);
+            if (col) {
+                u[0] += LA[0];
+                d2[0] += LA[1];
+                d0[0] += LA[2];
+                d1[0] += LA[3];
+                u[N - 1] += LB[0];
+                d2[N - 1] += LB[1];
+                d0[N - 1] += LB[2];
+                d1[N - 1] += LB[3];
+            }
+        }
     }
 
     // IProduct: y = B^T (m + D_0^T q_0 + D_1^T q_1 + D_2^T q_2)

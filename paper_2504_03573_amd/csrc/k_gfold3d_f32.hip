@@ -10,7 +10,7 @@ namespace {
 template <int P>
 hipError_t gfold_p(int mode, const g3::Args &A, const g3::Data<float> &D, hipStream_t st) {
     if (A.count <= 0) return hipSuccess;
-    const size_t lds = sizeof(float) * g3::lds_total<P>();
+    const size_t lds = sizeof(float) * g3::lds_total<P>(mode);
     if (mode == 0) hipLaunchKernelGGL((g3::k3g<float, P, 0>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else if (mode == 1) hipLaunchKernelGGL((g3::k3g<float, P, 1>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else hipLaunchKernelGGL((g3::k3g<float, P, 2>), dim3(A.count), dim3(g3::W), lds, st, A, D);
