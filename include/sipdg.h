@@ -138,7 +138,8 @@ int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int
  * receives the count):
  *   ms        mean duration over the reps,
  *   stage     1 (trace kernels) or 2 (apply kernels),
- *   order     the polynomial order of the launch's element group,
+ *   order     the polynomial order of the launch's element group (0 for
+ *             the persistent launch of all orders <= 6),
  *   elements  the elements it processes,
  *   alg_bytes the algorithmic bytes of those elements at this precision
  *             (stage 2 only, 0 for stage 1): each element's coefficients in
@@ -179,6 +180,11 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
  *              an order group above 6, or touching a neighbour above 6, uses
  *              the GATHER kernels (same trace buffer).  Default in 3-D
  *              (GATHER in 2-D).
+ *   GATHER_FOLD_PERSISTENT: as GATHER_FOLD, but each stage is one
+ *              persistent launch for the elements of every order <= 6 of all
+ *              problems (listed by decreasing order; a fixed number of blocks
+ *              per compute unit, chosen by sipdg_autotune, loops over them).
+ *              3-D.
  *   GATHER_FOLD_FUSED: as GATHER_FOLD, but the neighbour's traces are
  *              evaluated from its coefficients (TracePhysEval): one launch
  *              per order group, no trace buffer.  3-D, orders <= 6. */
@@ -187,7 +193,8 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
 #define SIPDG_VARIANT_FUSED             2
 #define SIPDG_VARIANT_GATHER_FOLD       3
 #define SIPDG_VARIANT_GATHER_FOLD_FUSED 4
-#define SIPDG_NUM_VARIANTS              5
+#define SIPDG_VARIANT_GATHER_FOLD_PERSISTENT 5
+#define SIPDG_NUM_VARIANTS              6
 int sipdg_set_variant(sipdg_handle h, int variant);   /* EINVAL if not allowed */
 int sipdg_get_variant(sipdg_handle h, int *variant);
 /* Time one FP64 application with every allowed variant (reps each, HIP

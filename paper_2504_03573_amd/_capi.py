@@ -25,7 +25,8 @@ SIPDG_F32 = 1
 SIPDG_CG_F64 = 0
 SIPDG_CG_F32_IR = 1
 MAX_ORDER = 8
-VARIANTS = {"gather": 0, "two_stage": 1, "fused": 2, "gather_fold": 3, "gather_fold_fused": 4}
+VARIANTS = {"gather": 0, "two_stage": 1, "fused": 2, "gather_fold": 3, "gather_fold_fused": 4,
+            "gather_fold_persistent": 5}
 
 c_int64_p = ctypes.POINTER(ctypes.c_int64)
 

@@ -127,8 +127,43 @@ static inline void rec_mark(LaunchRec *rec, int stage, int gi, bool after, hipSt
 }
 
 template <class R>
+hipError_t launch_gfold3d_persistent(int mode, int grid, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+
+template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
                LaunchRec *rec) {
+    if (c->variant == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT) {
+        for (int stage = 1; stage <= 2; ++stage) {
+            if (!(stages & stage)) continue;
+            // orders <= 6: one persistent launch over all of them
+            if (c->pcount > 0) {
+                f3::Args3 A3;
+                f3::Data3<R> D3;
+                fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
+                g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
+                           A3.skip, c->d_pdesc, c->d_pfdesc};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                rec_mark(rec, stage, -1, false, st);
+                hipError_t e = launch_gfold3d_persistent<R>(stage == 1 ? 0 : 1, c->num_cu * c->blocks_per_cu, A, D, st);
+                rec_mark(rec, stage, -1, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string("persistent kernel: ") + hipGetErrorString(e));
+            }
+            // the rest: the general kernels per group
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
+                if (g.P <= 6 && g.nfmax <= 8) continue;
+                OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+                rec_mark(rec, stage, (int)gi, false, st);
+                hipError_t e = launch_op<R>(c->dim, g.P, stage == 1 ? OP_TRACE : OP_APPLY, A, g.nfmax, st);
+                rec_mark(rec, stage, (int)gi, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
+                                                hipGetErrorString(e));
+            }
+        }
+        return SIPDG_OK;
+    }
     if (c->variant == SIPDG_VARIANT_GATHER_FOLD || c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED) {
         const bool fused = c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED;
         // the groups of a stage are independent: side streams, joined at the end
@@ -274,6 +309,8 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_dinv64, c->d_dinv32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (c->d_pdesc) (void)hipFree(c->d_pdesc);
+    if (c->d_pfdesc) (void)hipFree(c->d_pfdesc);
     for (hipStream_t sg : c->gstreams)
         if (sg) (void)hipStreamDestroy(sg);
     for (hipEvent_t ev : c->gevents)
@@ -458,6 +495,30 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
     {
         int pmax = 0;
         for (int o : T.order) pmax = std::max(pmax, o);
+        if (T.dim == 3) {
+            std::vector<ElemDesc> pd;
+            std::vector<FaceDesc> pf;
+            for (int P = 6; P >= 1; --P) {
+                for (const Group &g : c->groups) {
+                    if (g.P != P || g.nfmax > 8) continue;
+                    const size_t base = pd.size();
+                    pd.resize(base + g.count);
+                    pf.resize((base + g.count) * 6);
+                    TRYHIP(hipMemcpy(pd.data() + base, g.d_desc, sizeof(ElemDesc) * g.count, hipMemcpyDeviceToHost));
+                    TRYHIP(hipMemcpy(pf.data() + base * 6, g.d_fdesc, sizeof(FaceDesc) * 6 * g.count,
+                                     hipMemcpyDeviceToHost));
+                    for (int i = 0; i < g.count; ++i) pd[base + i].pad = P;
+                }
+            }
+            c->pcount = (int)pd.size();
+            if (!pd.empty()) {
+                TRY(upload(&c->d_pdesc, pd));
+                TRY(upload(&c->d_pfdesc, pf));
+            }
+            hipDeviceProp_t prop;
+            TRYHIP(hipGetDeviceProperties(&prop, c->device));
+            c->num_cu = prop.multiProcessorCount;
+        }
         if (c->groups.size() > 1) {
             c->gstreams.assign(c->groups.size(), nullptr);
             c->gevents.assign(c->groups.size() + 1, nullptr);
@@ -625,12 +686,24 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
                 }
                 sum += ms;
             }
-            const Group &g = h->groups[recs[0].group[i]];
             info[i].ms = sum / reps;
             info[i].stage = recs[0].stage[i];
-            info[i].order = g.P;
-            info[i].elements = g.count;
-            info[i].alg_bytes = info[i].stage == 2 ? g.alg_bytes[precision == SIPDG_F64 ? 0 : 1] : 0.0;
+            const int gi = recs[0].group[i];
+            const int w = precision == SIPDG_F64 ? 0 : 1;
+            if (gi >= 0) {
+                const Group &g = h->groups[gi];
+                info[i].order = g.P;
+                info[i].elements = g.count;
+                info[i].alg_bytes = info[i].stage == 2 ? g.alg_bytes[w] : 0.0;
+            } else {
+                // the persistent launch: every group of order <= 6 with traces <= 8 x 8
+                info[i].order = 0;
+                info[i].elements = h->pcount;
+                double ab = 0.0;
+                for (const Group &g : h->groups)
+                    if (g.P <= 6 && g.nfmax <= 8) ab += g.alg_bytes[w];
+                info[i].alg_bytes = info[i].stage == 2 ? ab : 0.0;
+            }
         }
     }
     *n_launches = n;
@@ -732,7 +805,7 @@ int sipdg_set_variant(sipdg_handle h, int variant) {
     }
     if (variant < 0 || variant >= SIPDG_NUM_VARIANTS)
         return fail(SIPDG_EINVAL, "unknown variant");
-    if (variant == SIPDG_VARIANT_GATHER_FOLD) {
+    if (variant == SIPDG_VARIANT_GATHER_FOLD || variant == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT) {
         if (!h->gfold_ok) return fail(SIPDG_EINVAL, "gather_fold needs a 3-D mesh");
     } else if (!h->fast_ok) {
         return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
@@ -764,18 +837,32 @@ int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
     int rc = SIPDG_OK;
     for (int v = 0; v < SIPDG_NUM_VARIANTS && rc == SIPDG_OK; ++v) {
         if (ms_out) ms_out[v] = 0.0;
-        if (v == SIPDG_VARIANT_GATHER_FOLD ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)) continue;
+        const bool gf = v == SIPDG_VARIANT_GATHER_FOLD || v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT;
+        if (gf ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)) continue;
         h->variant = v;
-        for (int i = 0; i < 3 && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
-        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SIPDG_EHIP, "event record");
-        for (int i = 0; i < reps && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) rc = fail(SIPDG_EHIP, "event sync");
-        float ms = 0.f;
-        if (rc == SIPDG_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
-            const double t = ms / reps;
-            if (ms_out) ms_out[v] = t;
-            if (t < best) {
-                best = t;
+        // the persistent launch also tunes its shape: blocks per compute unit
+        const int shapes[] = {2, 4, 6, 8, 12, 16};
+        const int nshape = v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT ? 6 : 1;
+        double vbest = 1e300;
+        int vshape = h->blocks_per_cu;
+        for (int si = 0; si < nshape && rc == SIPDG_OK; ++si) {
+            if (nshape > 1) h->blocks_per_cu = shapes[si];
+            for (int i = 0; i < 3 && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
+            if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SIPDG_EHIP, "event record");
+            for (int i = 0; i < reps && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                rc = fail(SIPDG_EHIP, "event sync");
+            float ms = 0.f;
+            if (rc == SIPDG_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms / reps < vbest) {
+                vbest = ms / reps;
+                vshape = h->blocks_per_cu;
+            }
+        }
+        if (nshape > 1) h->blocks_per_cu = vshape;
+        if (rc == SIPDG_OK && vbest < 1e300) {
+            if (ms_out) ms_out[v] = vbest;
+            if (vbest < best) {
+                best = vbest;
                 best_v = v;
             }
         }

@@ -130,6 +130,13 @@ struct sipdg_ctx {
     std::vector<hipStream_t> gstreams;
     std::vector<hipEvent_t> gevents;   // [0] fork, [1 + g] group g done
     bool concurrent = false;
+    // persistent gather-fold launch: every element of the order <= 6 groups
+    // (with traces <= 8 x 8), by decreasing order; ElemDesc::pad = order
+    sipdg::ElemDesc *d_pdesc = nullptr;
+    sipdg::FaceDesc *d_pfdesc = nullptr;
+    int pcount = 0;
+    int num_cu = 256;
+    int blocks_per_cu = 8;            // persistent grid = num_cu * blocks_per_cu
     bool fast_ok = false;   // 3-D with every order <= 6
     bool gfold_ok = false;  // 3-D: gather-fold for order <= 6 groups, general kernels above
 };

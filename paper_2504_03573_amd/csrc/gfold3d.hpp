@@ -776,23 +776,22 @@ __device__ __forceinline__ void face_store2(const Data<R> &D, const R *itl, cons
 //   trace buffer written by MODE 0 (the element's own face values and their
 //   interpolation are not needed again).
 // MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
+// One element: descriptor blk of A.desc / A.fdesc, LDS at smem_raw.
 template <class R, int P, int MODE>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g(Args A, Data<R> D) {
+__device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
     using S = Sz<P>;
     constexpr int N = S::N, NP = S::NP, NPTS = S::NPTS;
-    if (A.skip && *A.skip) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     R *SA = reinterpret_cast<R *>(smem_raw);
     R *SB = SA + S::ARR;
     R *FB = SA + FB_OFF;
-    const ElemDesc ed = A.desc[blockIdx.x];
+    const ElemDesc ed = A.desc[blk];
     const int64_t e = ed.e;
     const int l = threadIdx.x, a = l & 7, b = l >> 3;
     const bool col = a < N && b < N;
     const ctab<R> Bt = as_const(D.tab) + tab_off_B(P);   // [N][NP]
     const ctab<R> Dt = as_const(D.tab) + tab_off_D(N);   // [N][N]
     const int64_t xo = ed.xoff;
-    const MetaV<R> meta = load_meta<R, MODE>(A, D, blockIdx.x);
+    const MetaV<R> meta = load_meta<R, MODE>(A, D, blk);
     // interpolation tables of this order into LDS (read after several syncs)
     R *itl = SA + S::TOTAL;
 #pragma unroll
@@ -1248,6 +1247,45 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
             for (int j = 0; j < N; ++j) s += Bt[j * NP + i] * v[j];
             ye[i] = s;
         }
+    }
+}
+
+// One launch per order group: block b handles element b of the group.
+template <class R, int P, int MODE>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g(Args A, Data<R> D) {
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    k3g_elem<R, P, MODE>(A, D, blockIdx.x, smem_raw);
+}
+
+// LDS of the persistent kernel: the largest order's.
+template <int MODE>
+__host__ __device__ constexpr int lds_persistent() {
+    int m = 0;
+    const int v[6] = {lds_total<1>(MODE), lds_total<2>(MODE), lds_total<3>(MODE),
+                      lds_total<4>(MODE), lds_total<5>(MODE), lds_total<6>(MODE)};
+    for (int i = 0; i < 6; ++i) m = v[i] > m ? v[i] : m;
+    return m;
+}
+
+// One persistent launch for elements of every order <= 6: A.desc / A.fdesc
+// list them by decreasing order (the order in ElemDesc::pad); block b takes
+// elements b, b + gridDim.x, ... until the list ends, so every block exits.
+template <class R, int MODE>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g_persistent(Args A, Data<R> D) {
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    for (int i = blockIdx.x; i < A.count; i += gridDim.x) {
+        const int P = A.desc[i].pad;
+        switch (P) {
+        case 1: k3g_elem<R, 1, MODE>(A, D, i, smem_raw); break;
+        case 2: k3g_elem<R, 2, MODE>(A, D, i, smem_raw); break;
+        case 3: k3g_elem<R, 3, MODE>(A, D, i, smem_raw); break;
+        case 4: k3g_elem<R, 4, MODE>(A, D, i, smem_raw); break;
+        case 5: k3g_elem<R, 5, MODE>(A, D, i, smem_raw); break;
+        default: k3g_elem<R, 6, MODE>(A, D, i, smem_raw); break;
+        }
+        __syncthreads();   // the next element reuses the LDS
     }
 }
 

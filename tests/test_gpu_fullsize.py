@@ -54,7 +54,7 @@ def test_workload_sampled_rows(env, k):
     elems = np.sort(rng.choice(m.n_elems, size=300, replace=False))
     y_ref = om.apply(x, elems=elems)
     rows = _rows(om, om.dof_off, elems)
-    for v in (["gather", "two_stage", "fused", "gather_fold", "gather_fold_fused"] if op.variant != "gather" else ["gather"]):
+    for v in (["gather", "two_stage", "fused", "gather_fold", "gather_fold_fused", "gather_fold_persistent"] if op.variant != "gather" else ["gather"]):
         op.variant = v
         y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
         assert np.linalg.norm(y[rows] - y_ref[rows]) <= 1e-12 * np.linalg.norm(y_ref[rows]), v

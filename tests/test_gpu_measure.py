@@ -28,7 +28,7 @@ def _alg_bytes(st, dim, word):
     return word * words + 32 * (st["n_interior_faces"] + st["n_boundary_faces"])
 
 
-@pytest.mark.parametrize("variant", ["gather_fold", "two_stage", "gather"])
+@pytest.mark.parametrize("variant", ["gather_fold", "two_stage", "gather", "gather_fold_persistent"])
 def test_apply_timed(P, variant):
     print(f"[apply_timed {variant}]", flush=True)
     m = synth.workload(3, N=6)
@@ -42,6 +42,13 @@ def test_apply_timed(P, variant):
         xx = x.to(dt)
         y = torch.empty_like(xx)
         launches = op.apply_timed(xx, y, reps=3)
+        if variant == "gather_fold_persistent":
+            # one launch per stage for every order
+            assert [(L["stage"], L["order"], L["elements"]) for L in launches] == [(1, 0, m.n_elems), (2, 0, m.n_elems)]
+            assert sum(L["alg_bytes"] for L in launches) == pytest.approx(_alg_bytes(st, 3, word), rel=1e-12)
+            if dt == torch.float64:
+                assert torch.equal(y, y_ref)
+            continue
         assert len(launches) == 2 * groups
         assert [L["stage"] for L in launches] == [1] * groups + [2] * groups
         assert sorted(L["order"] for L in launches[groups:]) == sorted(set(m.order.tolist()))

@@ -170,18 +170,19 @@ def test_variants_agree(case):
     if int(mesh.order.max()) > 6:
         # gather-fold for orders <= 6 next to the general kernels above
         try:
-            for v in ("gather", "gather_fold"):
+            for v in ("gather", "gather_fold", "gather_fold_persistent"):
                 op.variant = v
                 ys[v] = op.apply(xt).cpu().numpy()
                 assert rel(ys[v], y_ref) <= 1e-12, v
             assert rel(ys["gather_fold"], ys["gather"]) <= 1e-13
+            assert rel(ys["gather_fold_persistent"], ys["gather_fold"]) <= 1e-14
             with pytest.raises(P_error()):
                 op.variant = "two_stage"
         finally:
             op.variant = keep
         return
     try:
-        for v in ("gather", "two_stage", "fused", "gather_fold", "gather_fold_fused"):
+        for v in ("gather", "two_stage", "fused", "gather_fold", "gather_fold_fused", "gather_fold_persistent"):
             op.variant = v
             ys[v] = op.apply(xt).cpu().numpy()
             assert rel(ys[v], y_ref) <= 1e-12, v
@@ -191,5 +192,6 @@ def test_variants_agree(case):
         assert rel(ys["two_stage"], ys["fused"]) <= 1e-14
         assert rel(ys["gather_fold"], ys["gather"]) <= 1e-13
         assert rel(ys["gather_fold_fused"], ys["gather_fold"]) <= 1e-14
+        assert rel(ys["gather_fold_persistent"], ys["gather_fold"]) <= 1e-14
     finally:
         op.variant = keep
