@@ -114,7 +114,7 @@ static void fast_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *t
 }
 
 template <class R>
-hipError_t launch_gfold3d(int P, int mode, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+hipError_t launch_gfold3d(int P, int mode, int nfmax, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 
 static inline void rec_mark(LaunchRec *rec, int stage, int gi, bool after, hipStream_t st) {
     if (!rec || rec->n >= rec->cap) return;
@@ -128,6 +128,14 @@ static inline void rec_mark(LaunchRec *rec, int stage, int gi, bool after, hipSt
 
 template <class R>
 hipError_t launch_gfold3d_persistent(int mode, int grid, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+
+// Can the gather-fold kernels take this order group?  One wavefront per
+// element up to order 6 with traces up to 8 x 8; two wavefronts for orders 7
+// and 8 (traces up to 10 x 10; not the fused kernel).
+static bool gfold_group(const Group &g, bool fused) {
+    if (g.P <= 6 && g.nfmax <= 8) return true;
+    return !fused && g.P >= 7 && g.P <= 8 && g.nfmax <= 10;
+}
 
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
@@ -149,13 +157,24 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 if (e != hipSuccess)
                     return fail(SIPDG_EHIP, std::string("persistent kernel: ") + hipGetErrorString(e));
             }
-            // the rest: the general kernels per group
+            // the rest: per group, gather-fold (orders 7, 8) or the general kernels
             for (size_t gi = 0; gi < c->groups.size(); ++gi) {
                 const Group &g = c->groups[gi];
                 if (g.P <= 6 && g.nfmax <= 8) continue;
-                OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
                 rec_mark(rec, stage, (int)gi, false, st);
-                hipError_t e = launch_op<R>(c->dim, g.P, stage == 1 ? OP_TRACE : OP_APPLY, A, g.nfmax, st);
+                hipError_t e;
+                if (gfold_group(g, false)) {
+                    f3::Args3 A3;
+                    f3::Data3<R> D3;
+                    fast_args<R>(c, g, x, y, tbuf, skip, false, A3, D3);
+                    g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
+                               A3.toff, A3.skip, g.d_desc, g.d_fdesc};
+                    g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                    e = launch_gfold3d<R>(g.P, stage == 1 ? 0 : 1, g.nfmax, A, D, st);
+                } else {
+                    OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+                    e = launch_op<R>(c->dim, g.P, stage == 1 ? OP_TRACE : OP_APPLY, A, g.nfmax, st);
+                }
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
                     return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
@@ -190,8 +209,8 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                         if (on) (void)hipEventRecord(ev, s);
                     }
                 } join{par, par ? c->gevents[1 + gi] : nullptr, st};
-                if (g.P > 6 || g.nfmax > 8) {
-                    // orders above 6, or a neighbour above 6 (a trace finer than the
+                if (!gfold_group(g, fused)) {
+                    // orders <= 6 next to orders above 6 (traces finer than the
                     // 8 x 8 lane grid): the general kernels, same trace-buffer layout
                     OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
                     rec_mark(rec, stage, (int)gi, false, st);
@@ -209,7 +228,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                            A3.skip, g.d_desc, g.d_fdesc};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
                 rec_mark(rec, stage, (int)gi, false, st);
-                hipError_t e = launch_gfold3d<R>(g.P, mode, A, D, st);
+                hipError_t e = launch_gfold3d<R>(g.P, mode, g.nfmax, A, D, st);
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
                     return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +

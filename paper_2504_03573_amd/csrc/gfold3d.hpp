@@ -1,7 +1,8 @@
-// Gather-fold hexahedron kernel, orders 1..6 (n = p+2 <= 8 GLL points per
-// direction) whose faces all have traces of at most 8 x 8 points (every
-// neighbour of order <= 6), one 64-lane wavefront per element, one launch per
-// order group.
+// Gather-fold hexahedron kernel, one launch per order group: orders 1..6
+// (n = p+2 <= 8 GLL points per direction) whose faces all have traces of at
+// most 8 x 8 points (every neighbour of order <= 6), one 64-lane wavefront
+// per element; orders 7 and 8 (traces up to 10 x 10), two wavefronts per
+// element.
 //
 // Volume terms (Xia & Moxey, Sec. 3.1 basic operators): lane (q0, q1) keeps
 // the xi_2 column of its n points in registers ("column layout").  BwdTrans,
@@ -11,8 +12,9 @@
 //   column  lane (q0, q1) holds (q0, q1, .)
 //   line-0  lane (q1, q2) holds (., q1, q2)
 //   line-1  lane (q0, q2) holds (q0, ., q2)
-// through two padded point arrays whose strides (9 along q1, 72/56/40/24 along
-// q2) keep the three access patterns on distinct LDS banks.
+// through two padded point arrays whose strides (9 along q1 (11 for n = 10),
+// and 24..120 along q2, odd multiples of 8) spread the three access patterns
+// over the LDS banks.
 //
 // Faces (Sec. 3.2 GathrInterp, Sec. 3.3 shared trace space): GLL points
 // include the element's faces, so u and grad_xi u at an element's own face
@@ -40,27 +42,42 @@
 namespace sipdg {
 namespace g3 {
 
-constexpr int W = 64;           // lanes per element
+constexpr int W = 64;           // lanes per element, orders <= 6
 constexpr int S9 = PMAX + 1;    // row stride of the BF/DBF tables
+
+// Lane geometry.  Orders <= 6: one 64-lane wavefront per element; lane l
+// holds point column / trace point (l % 8, l / 8); traces up to 8 x 8.
+// Orders 7 and 8 (9 x 9 and 10 x 10 columns, traces up to 10 x 10): two
+// wavefronts per element, lane l at (l % 10, l / 10).
+template <int P>
+struct Geo {
+    static constexpr int W = P <= 6 ? 64 : 128;     // threads per element
+    static constexpr int S = P <= 6 ? 8 : 10;       // lane stride of the 2-D grids
+    static constexpr int NFMAX = P <= 6 ? 8 : 10;   // largest trace per direction
+};
+template <int P>
+__device__ __forceinline__ int gx(int l) { return l % Geo<P>::S; }
+template <int P>
+__device__ __forceinline__ int gy(int l) { return l / Geo<P>::S; }
 
 template <int P>
 struct Sz {
     static constexpr int N = P + 2, NP = P + 1;
     static constexpr int NPTS = N * N * N;
-    static constexpr int S1 = 9;
-    static constexpr int S2 = N >= 7 ? 72 : (N >= 5 ? 56 : (N == 4 ? 40 : 24));
-    static constexpr int ARR = S2 * N;     // one padded point array
-    static constexpr int SCR = 1536;       // face scratch, aliases the point arrays
+    static constexpr int S1 = N <= 9 ? 9 : 11;   // odd and >= N
+    static constexpr int S2 = N == 10 ? 120 : (N == 9 ? 88 : (N >= 7 ? 72 : (N >= 5 ? 56 : (N == 4 ? 40 : 24))));
+    static_assert(S1 >= N && S2 >= S1 * (N - 1) + N, "point arrays must not overlap");
+    static constexpr int ARR = S2 * N;          // one padded point array
+    static constexpr int SCR = 24 * Geo<P>::W;  // face scratch, aliases the point arrays
     static constexpr int TOTAL = 2 * ARR > SCR ? 2 * ARR : SCR;
 };
 
-// face scratch (R units from the block's LDS base):
-//   FB [2 directions][2 sides][4 fields][64]  lifted flux of the faces normal
-//                                to xi_0 and xi_1, held until the pointwise terms
-//   NU [2][64], NW [3][64]       neighbour trace evaluation
-//   IS [4][64], IT [4][64]       interpolation to / from a finer trace (aliases NU, NW)
-constexpr int FB_OFF = 0, WK_OFF = 1024;
-constexpr int NU_OFF = WK_OFF, NW_OFF = WK_OFF + 128, IS_OFF = WK_OFF, IT_OFF = WK_OFF + 256;
+// face scratch (R units from the block's LDS base, W = Geo<P>::W):
+//   FB [2 sides][4 fields][W] at 0       lifted flux of the faces normal to xi_0
+//                                         or xi_1, for the column lanes
+//   [8 W, 24 W)                           interpolation / lift / neighbour work
+//   (the trace kernel uses [0, 16 W) for its interpolation)
+constexpr int FB_OFF = 0;
 
 struct Args {
     const int *elems;
@@ -99,12 +116,12 @@ __device__ __forceinline__ ctab<R> as_const(const R *p) {
     return (ctab<R>)p;
 }
 
-// LDS copy of the interpolation matrices I(n, m) [m][n] for m = n+1 .. 8,
-// the finer traces an element of order p can meet, concatenated by m.
+// LDS copy of the interpolation matrices I(n, m) [m][n] for m = n+1 .. the
+// largest trace, the finer traces an element of order p can meet, by m.
 template <int P>
 struct ITab {
-    static constexpr int N = P + 2;
-    static constexpr int SIZE = N < 8 ? N * ((8 * 9) / 2 - (N * (N + 1)) / 2) : 0;
+    static constexpr int N = P + 2, M = Geo<P>::NFMAX;
+    static constexpr int SIZE = N < M ? N * ((M * (M + 1)) / 2 - (N * (N + 1)) / 2) : 0;
 };
 template <int P>
 __device__ __forceinline__ int itab_off(int m) {
@@ -194,8 +211,8 @@ template <class R, int MODE>
 __device__ __forceinline__ MetaV<R> load_meta(const Args &A, const Data<R> &D, int blk) {
     MetaV<R> m;
     const int l = threadIdx.x;
-    if (l < 6) {
-        const FaceDesc fr = A.fdesc[(int64_t)blk * 6 + l];
+    if ((l & 63) < 6) {   // lanes 0..5 of every wavefront of the element
+        const FaceDesc fr = A.fdesc[(int64_t)blk * 6 + (l & 63)];
         m.F = fr.F;
         m.info = fr.info;
         m.fo = fr.fo;
@@ -255,12 +272,12 @@ struct FaceD {
 // boundary faces only the element's own.
 __device__ __forceinline__ int tb_side(int slot) { return slot == 1 ? 1 : 0; }
 
-template <class R, int MODE>
+template <class R, int P, int MODE>
 __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &u, int k) {
     FaceD<R> d;
     d.qc = 0;
     d.aw = d.Ck = d.Ca = d.Cb = d.n0 = d.n1 = d.n2 = d.ou = d.og = R(0);
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
     if (t1 >= u.nf || t2 >= u.nf) return d;
     const int npf = u.npf;
     d.qc = canon_index(u.o, u.nf, t1, t2);
@@ -295,62 +312,23 @@ __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &
 // Own u, grad_xi u at trace point (t1, t2): the face point itself when the
 // trace has the element's points, else interpolated with I (n_F x n) along
 // both face directions through LDS.
-template <class R, int P>
-__device__ __forceinline__ void own_trace(const R *itl, int nf, R *sm, R &u, R &dk, R &da, R &db) {
-    constexpr int N = P + 2;
-    if (nf == N) return;
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    R *IS = sm + IS_OFF, *IT = sm + IT_OFF;
-    const R *I = itl + itab_off<P>(nf);  // [nf][N] in LDS
-    if (t1 < N && t2 < N) {
-        IS[l] = u;
-        IS[W + l] = dk;
-        IS[2 * W + l] = da;
-        IS[3 * W + l] = db;
-    }
-    __syncthreads();
-    if (t1 < nf && t2 < N) {
-        R c[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const R w = I[t1 * N + j];
-#pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w * IS[f * W + j + 8 * t2];
-        }
-#pragma unroll
-        for (int f = 0; f < 4; ++f) IT[f * W + l] = c[f];
-    }
-    __syncthreads();
-    R c[4] = {0, 0, 0, 0};
-    if (t1 < nf && t2 < nf) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const R w = I[t2 * N + j];
-#pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w * IT[f * W + t1 + 8 * j];
-        }
-    }
-    u = c[0];
-    dk = c[1];
-    da = c[2];
-    db = c[3];
-    __syncthreads();
-}
-
 // The same for the two faces of one direction at once (scratch: 1024 R at sm).
 template <class R, int P>
 __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm, R vA[4], R vB[4]) {
+    constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
+    (void)WG;
+    (void)SG;
     constexpr int N = P + 2;
     const bool nA = nfA != N, nB = nfB != N;
     if (!nA && !nB) return;
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    R *ISA = sm, *ITA = sm + 4 * W, *ISB = sm + 8 * W, *ITB = sm + 12 * W;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
+    R *ISA = sm, *ITA = sm + 4 * WG, *ISB = sm + 8 * WG, *ITB = sm + 12 * WG;
     const R *IA = itl + itab_off<P>(nfA), *IB = itl + itab_off<P>(nfB);
     if (t1 < N && t2 < N) {
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            if (nA) ISA[f * W + l] = vA[f];
-            if (nB) ISB[f * W + l] = vB[f];
+            if (nA) ISA[f * WG + l] = vA[f];
+            if (nB) ISB[f * WG + l] = vB[f];
         }
     }
     __syncthreads();
@@ -360,10 +338,10 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
         for (int j = 0; j < N; ++j) {
             const R w = IA[t1 * N + j];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * W + j + 8 * t2];
+            for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * WG + j + SG * t2];
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ITA[f * W + l] = c[f];
+        for (int f = 0; f < 4; ++f) ITA[f * WG + l] = c[f];
     }
     if (nB && t1 < nfB && t2 < N) {
         R c[4] = {0, 0, 0, 0};
@@ -371,10 +349,10 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
         for (int j = 0; j < N; ++j) {
             const R w = IB[t1 * N + j];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * W + j + 8 * t2];
+            for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * WG + j + SG * t2];
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ITB[f * W + l] = c[f];
+        for (int f = 0; f < 4; ++f) ITB[f * WG + l] = c[f];
     }
     __syncthreads();
     if (nA) {
@@ -384,7 +362,7 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
             for (int j = 0; j < N; ++j) {
                 const R w = IA[t2 * N + j];
 #pragma unroll
-                for (int f = 0; f < 4; ++f) c[f] += w * ITA[f * W + t1 + 8 * j];
+                for (int f = 0; f < 4; ++f) c[f] += w * ITA[f * WG + t1 + SG * j];
             }
         }
 #pragma unroll
@@ -397,7 +375,7 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
             for (int j = 0; j < N; ++j) {
                 const R w = IB[t2 * N + j];
 #pragma unroll
-                for (int f = 0; f < 4; ++f) c[f] += w * ITB[f * W + t1 + 8 * j];
+                for (int f = 0; f < 4; ++f) c[f] += w * ITB[f * WG + t1 + SG * j];
             }
         }
 #pragma unroll
@@ -410,54 +388,57 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
 // direction back to the element's face points (scratch: 1024 R at sm).
 template <class R, int P>
 __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R LA[4], R LB[4]) {
+    constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
+    (void)WG;
+    (void)SG;
     constexpr int N = P + 2;
     const bool nA = nfA != N, nB = nfB != N;
     if (!nA && !nB) return;
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    R *ITA = sm, *ISA = sm + 4 * W, *ITB = sm + 8 * W, *ISB = sm + 12 * W;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
+    R *ITA = sm, *ISA = sm + 4 * WG, *ITB = sm + 8 * WG, *ISB = sm + 12 * WG;
     const R *IA = itl + itab_off<P>(nfA), *IB = itl + itab_off<P>(nfB);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        if (nA) ITA[f * W + l] = LA[f];
-        if (nB) ITB[f * W + l] = LB[f];
+        if (nA) ITA[f * WG + l] = LA[f];
+        if (nB) ITB[f * WG + l] = LB[f];
     }
     __syncthreads();
     if (nA && t1 < nfA && t2 < N) {
         R c[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < Geo<P>::NFMAX; ++t) {
             if (t < nfA) {
                 const R w = IA[t * N + t2];
 #pragma unroll
-                for (int f = 0; f < 4; ++f) c[f] += w * ITA[f * W + t1 + 8 * t];
+                for (int f = 0; f < 4; ++f) c[f] += w * ITA[f * WG + t1 + SG * t];
             }
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ISA[f * W + l] = c[f];
+        for (int f = 0; f < 4; ++f) ISA[f * WG + l] = c[f];
     }
     if (nB && t1 < nfB && t2 < N) {
         R c[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < Geo<P>::NFMAX; ++t) {
             if (t < nfB) {
                 const R w = IB[t * N + t2];
 #pragma unroll
-                for (int f = 0; f < 4; ++f) c[f] += w * ITB[f * W + t1 + 8 * t];
+                for (int f = 0; f < 4; ++f) c[f] += w * ITB[f * WG + t1 + SG * t];
             }
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ISB[f * W + l] = c[f];
+        for (int f = 0; f < 4; ++f) ISB[f * WG + l] = c[f];
     }
     __syncthreads();
     if (nA) {
         R c[4] = {0, 0, 0, 0};
         if (t1 < N && t2 < N) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < Geo<P>::NFMAX; ++t) {
                 if (t < nfA) {
                     const R w = IA[t * N + t1];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * W + t + 8 * t2];
+                    for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * WG + t + SG * t2];
                 }
             }
         }
@@ -468,11 +449,11 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
         R c[4] = {0, 0, 0, 0};
         if (t1 < N && t2 < N) {
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < Geo<P>::NFMAX; ++t) {
                 if (t < nfB) {
                     const R w = IB[t * N + t1];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * W + t + 8 * t2];
+                    for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * WG + t + SG * t2];
                 }
             }
         }
@@ -485,9 +466,9 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
 // Flux of eq. IP at this lane's trace point from both sides' (u, g) in the
 // trace buffer (apply kernel of the two-stage structure): this side's test
 // terms L = (F_v, F_g C_k, F_g C_a, F_g C_b), not yet lifted.
-template <class R>
+template <class R, int P>
 __device__ __forceinline__ void flux_tb(const FaceU<R> &fu, const FaceD<R> &fd, R L[4]) {
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
     R Fv = 0, Fg = 0;
     if (t1 < fu.nf && t2 < fu.nf) {
         const R un = fu.slot == 2 ? -fd.ou : fd.n0;   // mirrored exterior state on the boundary
@@ -502,78 +483,14 @@ __device__ __forceinline__ void flux_tb(const FaceU<R> &fu, const FaceD<R> &fd, 
     L[3] = Fg * fd.Cb;
 }
 
-// Neighbour's u and g = C_n . grad_xi u_n at this lane's trace point, from its
-// coefficients (TracePhysEval in the neighbour's face coordinates).
-template <class R>
-__device__ __forceinline__ void nbr_trace(const Data<R> &D, const FaceU<R> &fu, const FaceD<R> &fd, R *sm,
-                                          R &un, R &gn) {
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    const int nf = fu.nf, npn = fu.npn, kn = fu.kn, sn = fu.sn;
-    R *NU = sm + NU_OFF, *NW = sm + NW_OFF;
-    const R *__restrict__ xn = D.x + fu.xn;
-    if (t1 < npn && t2 < npn) {
-        R v0 = 0, v1 = 0;
-#pragma unroll
-        for (int ik = 0; ik < 7; ++ik) {
-            if (ik < npn) {
-                const R xv = xn[mode_rt(npn, kn, t1, t2, ik)];
-                v0 += end_val<R>(ik, sn) * xv;
-                v1 += end_der<R>(ik, sn) * xv;
-            }
-        }
-        NU[l] = v0;
-        NU[W + l] = v1;
-    }
-    __syncthreads();
-    const R *__restrict__ BF = D.tab + tab_off_BF(nf);
-    const R *__restrict__ DBF = D.tab + tab_off_DBF(nf);
-    if (t1 < nf && t2 < npn) {
-        R w0 = 0, w0d = 0, w1 = 0;
-#pragma unroll
-        for (int ia = 0; ia < 7; ++ia) {
-            if (ia < npn) {
-                const R bv = BF[t1 * S9 + ia], dv = DBF[t1 * S9 + ia];
-                const R x0 = NU[ia + 8 * t2], x1 = NU[W + ia + 8 * t2];
-                w0 += bv * x0;
-                w0d += dv * x0;
-                w1 += bv * x1;
-            }
-        }
-        NW[l] = w0;
-        NW[W + l] = w0d;
-        NW[2 * W + l] = w1;
-    }
-    __syncthreads();
-    un = gn = 0;
-    if (t1 < nf && t2 < nf) {
-        int r1, r2;
-        canon_inverse(fu.on, nf, fd.qc, r1, r2);
-        R vu = 0, vda = 0, vdb = 0, vdk = 0;
-#pragma unroll
-        for (int ib = 0; ib < 7; ++ib) {
-            if (ib < npn) {
-                const R bv = BF[r2 * S9 + ib], dv = DBF[r2 * S9 + ib];
-                const R w0 = NW[r1 + 8 * ib], w0d = NW[W + r1 + 8 * ib], w1 = NW[2 * W + r1 + 8 * ib];
-                vu += bv * w0;
-                vda += bv * w0d;
-                vdb += dv * w0;
-                vdk += bv * w1;
-            }
-        }
-        un = vu;
-        gn = fd.n0 * vdk + fd.n1 * vda + fd.n2 * vdb;
-    }
-    __syncthreads();
-}
-
 // Reduction of the neighbour's coefficients along its face normal with
 // P_i(s), P'_i(s) (first step of TracePhysEval), at lane (ia, ib) of its face
 // modes; zero elsewhere and on boundary faces.
-template <class R>
+template <class R, int P>
 __device__ __forceinline__ void nbr_reduce(const Data<R> &D, const FaceU<R> &fu, R &v0, R &v1) {
     v0 = v1 = R(0);
     if (fu.slot == 2) return;
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
     if (t1 < fu.npn && t2 < fu.npn) {
         const R *__restrict__ xn = D.x + fu.xn;
 #pragma unroll
@@ -595,15 +512,18 @@ template <class R, int P>
 __device__ __forceinline__ void nbr_pair(const R *btl, const FaceU<R> &fA, const FaceD<R> &dA, R a0, R a1,
                                          const FaceU<R> &fB, const FaceD<R> &dB, R b0, R b1, R *sm, R &unA,
                                          R &gnA, R &unB, R &gnB) {
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    R *NU = sm, *NWA = sm + 4 * W, *NWB = sm + 7 * W;
+    constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
+    (void)WG;
+    (void)SG;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
+    R *NU = sm, *NWA = sm + 4 * WG, *NWB = sm + 7 * WG;
     const bool iA = fA.slot != 2, iB = fB.slot != 2;
     unA = gnA = unB = gnB = R(0);
     if (!iA && !iB) return;
     NU[l] = a0;
-    NU[W + l] = a1;
-    NU[2 * W + l] = b0;
-    NU[3 * W + l] = b1;
+    NU[WG + l] = a1;
+    NU[2 * WG + l] = b0;
+    NU[3 * WG + l] = b1;
     __syncthreads();
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -611,7 +531,7 @@ __device__ __forceinline__ void nbr_pair(const R *btl, const FaceU<R> &fA, const
         if (side ? !iB : !iA) continue;
         if (t1 < f.nf && t2 < f.npn) {
             const R *bf = btl + btab_off<P>(f.nf) + 7 * t1, *dbf = bf + 7 * f.nf;
-            const R *u0 = NU + 2 * side * W + 8 * t2, *u1 = u0 + W;
+            const R *u0 = NU + 2 * side * WG + SG * t2, *u1 = u0 + WG;
             R w0 = 0, w0d = 0, w1 = 0;
 #pragma unroll
             for (int ia = 0; ia < 7; ++ia) {
@@ -624,8 +544,8 @@ __device__ __forceinline__ void nbr_pair(const R *btl, const FaceU<R> &fA, const
             }
             R *nw = side ? NWB : NWA;
             nw[l] = w0;
-            nw[W + l] = w0d;
-            nw[2 * W + l] = w1;
+            nw[WG + l] = w0d;
+            nw[2 * WG + l] = w1;
         }
     }
     __syncthreads();
@@ -643,11 +563,11 @@ __device__ __forceinline__ void nbr_pair(const R *btl, const FaceU<R> &fA, const
 #pragma unroll
             for (int ib = 0; ib < 7; ++ib) {
                 if (ib < f.npn) {
-                    const R bv = bf[ib], w0 = nw[8 * ib];
+                    const R bv = bf[ib], w0 = nw[SG * ib];
                     vu += bv * w0;
-                    vda += bv * nw[W + 8 * ib];
+                    vda += bv * nw[WG + SG * ib];
                     vdb += dbf[ib] * w0;
-                    vdk += bv * nw[2 * W + 8 * ib];
+                    vdk += bv * nw[2 * WG + SG * ib];
                 }
             }
             const R un = vu, gn = d.n0 * vdk + d.n1 * vda + d.n2 * vdb;
@@ -666,9 +586,9 @@ __device__ __forceinline__ void nbr_pair(const R *btl, const FaceU<R> &fA, const
 // Flux of eq. IP at this lane's trace point from the element's own (u, g) and
 // the neighbour's (or the mirrored state on the boundary): this side's test
 // terms L = (F_v, F_g C_k, F_g C_a, F_g C_b), not yet lifted.
-template <class R>
+template <class R, int P>
 __device__ __forceinline__ void flux_own(const FaceU<R> &fu, const FaceD<R> &fd, R u, R g, R un, R gn, R L[4]) {
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
     R Fv = 0, Fg = 0;
     if (t1 < fu.nf && t2 < fu.nf) {
         if (fu.slot == 2) {
@@ -696,58 +616,9 @@ __device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, cons
     const R gB = dB.Ck * vB[1] + dB.Ca * vB[2] + dB.Cb * vB[3];
     R unA, gnA, unB, gnB;
     nbr_pair<R, P>(btl, fA, dA, a0, a1, fB, dB, b0, b1, sm, unA, gnA, unB, gnB);
-    flux_own<R>(fA, dA, vA[0], gA, unA, gnA, LA);
-    flux_own<R>(fB, dB, vB[0], gB, unB, gnB, LB);
+    flux_own<R, P>(fA, dA, vA[0], gA, unA, gnA, LA);
+    flux_own<R, P>(fB, dB, vB[0], gB, unB, gnB, LB);
     lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
-}
-
-// Lift of the flux of one face at this lane's own face point.  In: the
-// element's u, d_k u, d_a u, d_b u at its face point (a, b) = lane (valid for
-// a, b < n).  Out: L = (F_v, F_g C_k, F_g C_a, F_g C_b) at the same point, the
-// terms that multiply phi and d_k phi, d_a phi, d_b phi.
-template <class R, int P, int MODE>
-__device__ __forceinline__ void face_lift(const Data<R> &D, const R *itl, const FaceU<R> &fu, const FaceD<R> &fd,
-                                          R ou, R odk, R oda, R odb, R *sm, R L[4]) {
-    constexpr int N = P + 2;
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
-    const int nf = fu.nf;
-    const bool tin = t1 < nf && t2 < nf;
-    R u, g;
-    if (MODE == 1) {
-        u = fd.ou;
-        g = fd.og;
-    } else {
-        R dk = odk, da = oda, db = odb;
-        u = ou;
-        own_trace<R, P>(itl, nf, sm, u, dk, da, db);
-        g = fd.Ck * dk + fd.Ca * da + fd.Cb * db;
-    }
-    R un, gn;
-    if (fu.slot == 2) {
-        un = -u;   // mirrored exterior state
-        gn = -g;
-    } else if (MODE == 1) {
-        un = fd.n0;
-        gn = fd.n1;
-    } else {
-        nbr_trace<R>(D, fu, fd, sm, un, gn);
-    }
-    // flux of eq. IP at the trace point, this side's test terms
-    R Fv = 0, Fg = 0;
-    if (tin) {
-        const R jump = u - un;
-        Fv = R(-0.5) * (g - gn) + fu.tau * fd.aw * jump;
-        Fg = R(-0.5) * jump;
-    }
-    L[0] = Fv;
-    L[1] = Fg * fd.Ck;
-    L[2] = Fg * fd.Ca;
-    L[3] = Fg * fd.Cb;
-    if (nf != N) {
-        // transposed interpolation back to the element's face points
-        R LB[4] = {0, 0, 0, 0};
-        lift2<R, P>(itl, nf, N, sm + IS_OFF, L, LB);
-    }
 }
 
 // Traces of the two faces of one direction: (u, g) at the trace points in
@@ -756,7 +627,10 @@ template <class R, int P>
 __device__ __forceinline__ void face_store2(const Data<R> &D, const R *itl, const FaceU<R> &fA,
                                             const FaceD<R> &dA, R vA[4], const FaceU<R> &fB, const FaceD<R> &dB,
                                             R vB[4], R *sm) {
-    const int l = threadIdx.x, t1 = l & 7, t2 = l >> 3;
+    constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
+    (void)WG;
+    (void)SG;
+    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
     own_trace2<R, P>(itl, fA.nf, fB.nf, sm, vA, vB);
     if (t1 < fA.nf && t2 < fA.nf) {
         R *__restrict__ tb = D.tbuf + fA.to + tb_side(fA.slot) * 2 * fA.npf + dA.qc;
@@ -779,6 +653,9 @@ __device__ __forceinline__ void face_store2(const Data<R> &D, const R *itl, cons
 // One element: descriptor blk of A.desc / A.fdesc, LDS at smem_raw.
 template <class R, int P, int MODE>
 __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
+    constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
+    (void)WG;
+    (void)SG;
     using S = Sz<P>;
     constexpr int N = S::N, NP = S::NP, NPTS = S::NPTS;
     R *SA = reinterpret_cast<R *>(smem_raw);
@@ -786,7 +663,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     R *FB = SA + FB_OFF;
     const ElemDesc ed = A.desc[blk];
     const int64_t e = ed.e;
-    const int l = threadIdx.x, a = l & 7, b = l >> 3;
+    const int l = threadIdx.x, a = gx<P>(l), b = gy<P>(l);
     const bool col = a < N && b < N;
     const ctab<R> Bt = as_const(D.tab) + tab_off_B(P);   // [N][NP]
     const ctab<R> Dt = as_const(D.tab) + tab_off_D(N);   // [N][N]
@@ -795,9 +672,9 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     // interpolation tables of this order into LDS (read after several syncs)
     R *itl = SA + S::TOTAL;
 #pragma unroll
-    for (int m = N + 1; m <= 8; ++m) {
+    for (int m = N + 1; m <= Geo<P>::NFMAX; ++m) {
         const R *__restrict__ src = D.tab + tab_off_I(N, m);
-        for (int i = l; i < m * N; i += W) itl[itab_off<P>(m) + i] = src[i];
+        for (int i = l; i < m * N; i += WG) itl[itab_off<P>(m) + i] = src[i];
     }
     // fused: the trace tables, and every neighbour's face-normal reduction
     // (their coefficient loads in flight together, during the volume work)
@@ -807,13 +684,13 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
 #pragma unroll
         for (int m = N; m <= 8; ++m) {
             const R *__restrict__ bf = D.tab + tab_off_BF(m), *__restrict__ dbf = D.tab + tab_off_DBF(m);
-            for (int i = l; i < 7 * m; i += W) {
+            for (int i = l; i < 7 * m; i += WG) {
                 btl[btab_off<P>(m) + i] = bf[(i / 7) * S9 + i % 7];
                 btl[btab_off<P>(m) + 7 * m + i] = dbf[(i / 7) * S9 + i % 7];
             }
         }
 #pragma unroll
-        for (int f = 0; f < (MODE == 2 ? 6 : 0); ++f) nbr_reduce<R>(D, face_uniform<R>(meta, f), nv0[f], nv1[f]);
+        for (int f = 0; f < (MODE == 2 ? 6 : 0); ++f) nbr_reduce<R, P>(D, face_uniform<R>(meta, f), nv0[f], nv1[f]);
     }
     // trace kernel: every face's per-point data in flight from the start
     FaceU<R> tu[MODE == 0 ? 6 : 1];
@@ -822,7 +699,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
 #pragma unroll
         for (int f = 0; f < (MODE == 0 ? 6 : 0); ++f) {
             tu[f] = face_uniform<R>(meta, f);
-            td[f] = load_face<R, 0>(D, tu[f], f >> 1);
+            td[f] = load_face<R, P, 0>(D, tu[f], f >> 1);
         }
     }
 
@@ -890,9 +767,9 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     FaceD<R> fd0, fd1;
     if (MODE != 0) {
         fu0 = face_uniform<R>(meta, 0);
-        fd0 = load_face<R, MODE>(D, fu0, 0);
+        fd0 = load_face<R, P, MODE>(D, fu0, 0);
         fu1 = face_uniform<R>(meta, 1);
-        fd1 = load_face<R, MODE>(D, fu1, 0);
+        fd1 = load_face<R, P, MODE>(D, fu1, 0);
     }
     // d_0 u on line-0 lanes (q1, q2) = (a, b), d_1 u on line-1 lanes (q0, q2) = (a, b);
     // keep the faces' values at the line ends
@@ -1005,59 +882,59 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
         // Normal to xi_0: own points (q1, q2) on column lanes q0 = 0, n-1.
         {
             R LA[4], LB[4];
-            flux_tb<R>(fu0, fd0, LA);
-            flux_tb<R>(fu1, fd1, LB);
+            flux_tb<R, P>(fu0, fd0, LA);
+            flux_tb<R, P>(fu1, fd1, LB);
             const FaceU<R> fu2 = face_uniform<R>(meta, 2);
-            const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
+            const FaceD<R> fd2 = load_face<R, P, MODE>(D, fu2, 1);
             const FaceU<R> fu3 = face_uniform<R>(meta, 3);
-            const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
-            lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 512, LA, LB);
+            const FaceD<R> fd3 = load_face<R, P, MODE>(D, fu3, 1);
+            lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 8 * WG, LA, LB);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                FB[f * W + l] = LA[f];
-                FB[4 * W + f * W + l] = LB[f];
+                FB[f * WG + l] = LA[f];
+                FB[4 * WG + f * WG + l] = LB[f];
             }
             __syncthreads();
             if (col && (a == 0 || a == N - 1)) {
-                const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
+                const R *fb = FB + (a == 0 ? 0 : 4 * WG) + b;
 #pragma unroll
                 for (int q = 0; q < N; ++q) {
-                    u[q] += fb[8 * q];
-                    d0[q] += fb[W + 8 * q];
-                    d1[q] += fb[2 * W + 8 * q];
-                    d2[q] += fb[3 * W + 8 * q];
+                    u[q] += fb[SG * q];
+                    d0[q] += fb[WG + SG * q];
+                    d1[q] += fb[2 * WG + SG * q];
+                    d2[q] += fb[3 * WG + SG * q];
                 }
             }
             __syncthreads();
             // normal to xi_1: own points (q0, q2) on column lanes q1 = 0, n-1
-            flux_tb<R>(fu2, fd2, LA);
-            flux_tb<R>(fu3, fd3, LB);
+            flux_tb<R, P>(fu2, fd2, LA);
+            flux_tb<R, P>(fu3, fd3, LB);
             fu0 = face_uniform<R>(meta, 4);
-            fd0 = load_face<R, MODE>(D, fu0, 2);
+            fd0 = load_face<R, P, MODE>(D, fu0, 2);
             fu1 = face_uniform<R>(meta, 5);
-            fd1 = load_face<R, MODE>(D, fu1, 2);
-            lift2<R, P>(itl, fu2.nf, fu3.nf, SA + 512, LA, LB);
+            fd1 = load_face<R, P, MODE>(D, fu1, 2);
+            lift2<R, P>(itl, fu2.nf, fu3.nf, SA + 8 * WG, LA, LB);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                FB[f * W + l] = LA[f];
-                FB[4 * W + f * W + l] = LB[f];
+                FB[f * WG + l] = LA[f];
+                FB[4 * WG + f * WG + l] = LB[f];
             }
             __syncthreads();
             if (col && (b == 0 || b == N - 1)) {
-                const R *fb = FB + (b == 0 ? 0 : 4 * W) + a;
+                const R *fb = FB + (b == 0 ? 0 : 4 * WG) + a;
 #pragma unroll
                 for (int q = 0; q < N; ++q) {
-                    u[q] += fb[8 * q];
-                    d1[q] += fb[W + 8 * q];
-                    d0[q] += fb[2 * W + 8 * q];
-                    d2[q] += fb[3 * W + 8 * q];
+                    u[q] += fb[SG * q];
+                    d1[q] += fb[WG + SG * q];
+                    d0[q] += fb[2 * WG + SG * q];
+                    d2[q] += fb[3 * WG + SG * q];
                 }
             }
             __syncthreads();
             // normal to xi_2: own points (q0, q1) are the column ends
-            flux_tb<R>(fu0, fd0, LA);
-            flux_tb<R>(fu1, fd1, LB);
-            lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 512, LA, LB);
+            flux_tb<R, P>(fu0, fd0, LA);
+            flux_tb<R, P>(fu1, fd1, LB);
+            lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 8 * WG, LA, LB);
             if (col) {
                 u[0] += LA[0];
                 d2[0] += LA[1];
@@ -1092,57 +969,57 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
         R LA[4], LB[4];
         {
             const FaceU<R> fu2 = face_uniform<R>(meta, 2);
-            const FaceD<R> fd2 = load_face<R, MODE>(D, fu2, 1);
+            const FaceD<R> fd2 = load_face<R, P, MODE>(D, fu2, 1);
             const FaceU<R> fu3 = face_uniform<R>(meta, 3);
-            const FaceD<R> fd3 = load_face<R, MODE>(D, fu3, 1);
+            const FaceD<R> fd3 = load_face<R, P, MODE>(D, fu3, 1);
             R vA[4] = {x_u[0], x_dk[0], x_da[0], x_db[0]}, vB[4] = {x_u[1], x_dk[1], x_da[1], x_db[1]};
-            face_pair_fused<R, P>(itl, btl, fu0, fd0, vA, nv0[0], nv1[0], fu1, fd1, vB, nv0[1], nv1[1], SA + 512,
+            face_pair_fused<R, P>(itl, btl, fu0, fd0, vA, nv0[0], nv1[0], fu1, fd1, vB, nv0[1], nv1[1], SA + 8 * WG,
                                   LA, LB);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                FB[f * W + l] = LA[f];
-                FB[4 * W + f * W + l] = LB[f];
+                FB[f * WG + l] = LA[f];
+                FB[4 * WG + f * WG + l] = LB[f];
             }
             __syncthreads();
             if (col && (a == 0 || a == N - 1)) {
-                const R *fb = FB + (a == 0 ? 0 : 4 * W) + b;
+                const R *fb = FB + (a == 0 ? 0 : 4 * WG) + b;
 #pragma unroll
                 for (int q = 0; q < N; ++q) {
-                    u[q] += fb[8 * q];
-                    d0[q] += fb[W + 8 * q];
-                    d1[q] += fb[2 * W + 8 * q];
-                    d2[q] += fb[3 * W + 8 * q];
+                    u[q] += fb[SG * q];
+                    d0[q] += fb[WG + SG * q];
+                    d1[q] += fb[2 * WG + SG * q];
+                    d2[q] += fb[3 * WG + SG * q];
                 }
             }
             __syncthreads();
             fu0 = face_uniform<R>(meta, 4);
-            fd0 = load_face<R, MODE>(D, fu0, 2);
+            fd0 = load_face<R, P, MODE>(D, fu0, 2);
             fu1 = face_uniform<R>(meta, 5);
-            fd1 = load_face<R, MODE>(D, fu1, 2);
+            fd1 = load_face<R, P, MODE>(D, fu1, 2);
             R wA[4] = {y_u[0], y_dk[0], y_da[0], y_db[0]}, wB[4] = {y_u[1], y_dk[1], y_da[1], y_db[1]};
-            face_pair_fused<R, P>(itl, btl, fu2, fd2, wA, nv0[2], nv1[2], fu3, fd3, wB, nv0[3], nv1[3], SA + 512,
+            face_pair_fused<R, P>(itl, btl, fu2, fd2, wA, nv0[2], nv1[2], fu3, fd3, wB, nv0[3], nv1[3], SA + 8 * WG,
                                   LA, LB);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
-                FB[f * W + l] = LA[f];
-                FB[4 * W + f * W + l] = LB[f];
+                FB[f * WG + l] = LA[f];
+                FB[4 * WG + f * WG + l] = LB[f];
             }
             __syncthreads();
             if (col && (b == 0 || b == N - 1)) {
-                const R *fb = FB + (b == 0 ? 0 : 4 * W) + a;
+                const R *fb = FB + (b == 0 ? 0 : 4 * WG) + a;
 #pragma unroll
                 for (int q = 0; q < N; ++q) {
-                    u[q] += fb[8 * q];
-                    d1[q] += fb[W + 8 * q];
-                    d0[q] += fb[2 * W + 8 * q];
-                    d2[q] += fb[3 * W + 8 * q];
+                    u[q] += fb[SG * q];
+                    d1[q] += fb[WG + SG * q];
+                    d0[q] += fb[2 * WG + SG * q];
+                    d2[q] += fb[3 * WG + SG * q];
                 }
             }
             __syncthreads();
         }
         {
             R vA[4] = {z_u[0], z_dk[0], z_da[0], z_db[0]}, vB[4] = {z_u[1], z_dk[1], z_da[1], z_db[1]};
-            face_pair_fused<R, P>(itl, btl, fu0, fd0, vA, nv0[4], nv1[4], fu1, fd1, vB, nv0[5], nv1[5], SA + 512,
+            face_pair_fused<R, P>(itl, btl, fu0, fd0, vA, nv0[4], nv1[4], fu1, fd1, vB, nv0[5], nv1[5], SA + 8 * WG,
                                   LA, LB);
             if (col) {
                 u[0] += LA[0];
@@ -1252,7 +1129,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
 
 // One launch per order group: block b handles element b of the group.
 template <class R, int P, int MODE>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g(Args A, Data<R> D) {
+__global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(2))) void k3g(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     k3g_elem<R, P, MODE>(A, D, blockIdx.x, smem_raw);

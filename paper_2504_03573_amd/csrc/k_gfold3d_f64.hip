@@ -1,34 +1,40 @@
-// Gather-fold hexahedron kernel (double), orders 1..6: one launch per order group.
+// Gather-fold hexahedron kernel (double), orders 1..8: one launch per order group.
 #include "gfold3d.hpp"
 
 namespace sipdg {
 
 template <class R>
-hipError_t launch_gfold3d(int P, int mode, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+hipError_t launch_gfold3d(int P, int mode, int nfmax, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 template <class R>
 hipError_t launch_gfold3d_persistent(int mode, int grid, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 
 namespace {
 template <int P>
-hipError_t gfold_p(int mode, const g3::Args &A, const g3::Data<double> &D, hipStream_t st) {
+hipError_t gfold_p(int mode, int nfmax, const g3::Args &A, const g3::Data<double> &D, hipStream_t st) {
+    // the lane grid covers traces up to NFMAX x NFMAX points
+    if (nfmax > g3::Geo<P>::NFMAX) return hipErrorInvalidValue;
     if (A.count <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * g3::lds_total<P>(mode);
-    if (mode == 0) hipLaunchKernelGGL((g3::k3g<double, P, 0>), dim3(A.count), dim3(g3::W), lds, st, A, D);
-    else if (mode == 1) hipLaunchKernelGGL((g3::k3g<double, P, 1>), dim3(A.count), dim3(g3::W), lds, st, A, D);
-    else hipLaunchKernelGGL((g3::k3g<double, P, 2>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    const dim3 blk(g3::Geo<P>::W);
+    if (mode == 0) hipLaunchKernelGGL((g3::k3g<double, P, 0>), dim3(A.count), blk, lds, st, A, D);
+    else if (mode == 1) hipLaunchKernelGGL((g3::k3g<double, P, 1>), dim3(A.count), blk, lds, st, A, D);
+    else if constexpr (P <= 6) hipLaunchKernelGGL((g3::k3g<double, P, 2>), dim3(A.count), blk, lds, st, A, D);
+    else return hipErrorInvalidValue;   // the fused kernel covers orders <= 6
     return hipGetLastError();
 }
 }  // namespace
 
 template <>
-hipError_t launch_gfold3d<double>(int P, int mode, const g3::Args &A, const g3::Data<double> &D, hipStream_t st) {
+hipError_t launch_gfold3d<double>(int P, int mode, int nfmax, const g3::Args &A, const g3::Data<double> &D, hipStream_t st) {
     switch (P) {
-    case 1: return gfold_p<1>(mode, A, D, st);
-    case 2: return gfold_p<2>(mode, A, D, st);
-    case 3: return gfold_p<3>(mode, A, D, st);
-    case 4: return gfold_p<4>(mode, A, D, st);
-    case 5: return gfold_p<5>(mode, A, D, st);
-    case 6: return gfold_p<6>(mode, A, D, st);
+    case 1: return gfold_p<1>(mode, nfmax, A, D, st);
+    case 2: return gfold_p<2>(mode, nfmax, A, D, st);
+    case 3: return gfold_p<3>(mode, nfmax, A, D, st);
+    case 4: return gfold_p<4>(mode, nfmax, A, D, st);
+    case 5: return gfold_p<5>(mode, nfmax, A, D, st);
+    case 6: return gfold_p<6>(mode, nfmax, A, D, st);
+    case 7: return gfold_p<7>(mode, nfmax, A, D, st);
+    case 8: return gfold_p<8>(mode, nfmax, A, D, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -48,6 +48,8 @@ CASES = {
     "3d_random_p1to4_rot": lambda: synth.small_mesh(3, 3, ("random", 1, 4), seed=5, rotate=True, lam=1.5),
     "3d_random_p3to6_n4": lambda: synth.workload(3, N=4),
     "3d_p5to8_n2": lambda: synth.small_mesh(3, 2, ("random", 5, 8), seed=9, rotate=True, lam=0.5),
+    "3d_p7_n2_rot": lambda: synth.small_mesh(3, 2, 7, seed=13, rotate=True, lam=2.0),
+    "3d_checker78_n3": lambda: synth.small_mesh(3, 3, ("checker", 7, 8), seed=17, lam=1.0),
     "3d_single_elem_p2": lambda: synth.small_mesh(3, 1, 2, seed=1, lam=3.0),
     "w5_lamfield_n3": lambda: synth.workload(5, N=3),
 }
