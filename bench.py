@@ -86,7 +86,9 @@ def source_hash():
 def kernel_name(variant, order, stage=2):
     """Kernel symbol (as rocprofv3 prints it, FP64) of one launch."""
     if variant == "gather_fold":
-        return "sipdg::g3::k3g<double, %d, %d>" % (order, 0 if stage == 1 else 1)
+        if stage == 1:
+            return "sipdg::g3::k3t_all<double>" if order == 0 else "sipdg::g3::k3t<double, %d>" % order
+        return "sipdg::g3::k3g<double, %d, 1>" % order
     if variant == "gather_fold_persistent" and order == 0:
         return "sipdg::g3::k3g_persistent<double, %d>" % (0 if stage == 1 else 1)
     if variant == "gather_fold_fused":

@@ -128,6 +128,8 @@ static inline void rec_mark(LaunchRec *rec, int stage, int gi, bool after, hipSt
 
 template <class R>
 hipError_t launch_gfold3d_persistent(int mode, int grid, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+template <class R>
+hipError_t launch_gfold3d_trace_all(const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 
 // Can the gather-fold kernels take this order group?  One wavefront per
 // element up to order 6 with traces up to 8 x 8; two wavefronts for orders 7
@@ -194,10 +196,25 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
         for (int stage = 1; stage <= 2; ++stage) {
             if (!(stages & stage) || (fused && stage == 1)) continue;
             const int mode = stage == 1 ? 0 : (fused ? 2 : 1);
+            // trace stage of the order <= 6 groups (traces <= 8 x 8): one launch
+            const bool merged = stage == 1 && c->pcount > 0;
+            if (merged) {
+                f3::Args3 A3;
+                f3::Data3<R> D3;
+                fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
+                g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
+                           A3.skip, c->d_pdesc, c->d_pfdesc};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                rec_mark(rec, stage, -1, false, main_st);
+                hipError_t e = launch_gfold3d_trace_all<R>(A, D, main_st);
+                rec_mark(rec, stage, -1, true, main_st);
+                if (e != hipSuccess) return fail(SIPDG_EHIP, std::string("trace kernel: ") + hipGetErrorString(e));
+            }
             if (par && hipEventRecord(c->gevents[0], main_st) != hipSuccess)
                 return fail(SIPDG_EHIP, "event record (fork)");
             for (size_t gi = 0; gi < c->groups.size(); ++gi) {
                 const Group &g = c->groups[gi];
+                if (merged && g.P <= 6 && g.nfmax <= 8) continue;
                 hipStream_t st = par ? c->gstreams[gi] : main_st;
                 if (par && hipStreamWaitEvent(st, c->gevents[0], 0) != hipSuccess)
                     return fail(SIPDG_EHIP, "stream wait (fork)");

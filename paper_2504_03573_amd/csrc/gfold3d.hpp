@@ -34,6 +34,10 @@
 // for the phi test term and a vector for the grad phi test term -- is added to
 // the volume's pointwise terms at the face points, so the inner product with
 // the basis (IProduct) lifts faces and volume at once and y is written once.
+//
+// Trace stage of the two-stage structure (k3t_elem): no volume work; the
+// element's own u and grad_xi u at its trace points come from the same face
+// reduction and two contractions as the neighbour's evaluation above.
 #pragma once
 
 #include "context.hpp"
@@ -76,7 +80,6 @@ struct Sz {
 //   FB [2 sides][4 fields][W] at 0       lifted flux of the faces normal to xi_0
 //                                         or xi_1, for the column lanes
 //   [8 W, 24 W)                           interpolation / lift / neighbour work
-//   (the trace kernel uses [0, 16 W) for its interpolation)
 constexpr int FB_OFF = 0;
 
 struct Args {
@@ -621,31 +624,7 @@ __device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, cons
     lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
 }
 
-// Traces of the two faces of one direction: (u, g) at the trace points in
-// canonical order, into the trace buffer (this side's slot).
-template <class R, int P>
-__device__ __forceinline__ void face_store2(const Data<R> &D, const R *itl, const FaceU<R> &fA,
-                                            const FaceD<R> &dA, R vA[4], const FaceU<R> &fB, const FaceD<R> &dB,
-                                            R vB[4], R *sm) {
-    constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
-    (void)WG;
-    (void)SG;
-    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
-    own_trace2<R, P>(itl, fA.nf, fB.nf, sm, vA, vB);
-    if (t1 < fA.nf && t2 < fA.nf) {
-        R *__restrict__ tb = D.tbuf + fA.to + tb_side(fA.slot) * 2 * fA.npf + dA.qc;
-        tb[0] = vA[0];
-        tb[fA.npf] = dA.Ck * vA[1] + dA.Ca * vA[2] + dA.Cb * vA[3];
-    }
-    if (t1 < fB.nf && t2 < fB.nf) {
-        R *__restrict__ tb = D.tbuf + fB.to + tb_side(fB.slot) * 2 * fB.npf + dB.qc;
-        tb[0] = vB[0];
-        tb[fB.npf] = dB.Ck * vB[1] + dB.Ca * vB[2] + dB.Cb * vB[3];
-    }
-}
-
-// MODE 0 (trace kernel): (u, g) of every face side of the element at the trace
-//   points into the trace buffer.
+// (The trace stage is k3t_elem.)
 // MODE 1 (apply, two-stage): y = A x with both sides' (u, g) read from the
 //   trace buffer written by MODE 0 (the element's own face values and their
 //   interpolation are not needed again).
@@ -691,16 +670,6 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
         }
 #pragma unroll
         for (int f = 0; f < (MODE == 2 ? 6 : 0); ++f) nbr_reduce<R, P>(D, face_uniform<R>(meta, f), nv0[f], nv1[f]);
-    }
-    // trace kernel: every face's per-point data in flight from the start
-    FaceU<R> tu[MODE == 0 ? 6 : 1];
-    FaceD<R> td[MODE == 0 ? 6 : 1];
-    if (MODE == 0) {
-#pragma unroll
-        for (int f = 0; f < (MODE == 0 ? 6 : 0); ++f) {
-            tu[f] = face_uniform<R>(meta, f);
-            td[f] = load_face<R, P, 0>(D, tu[f], f >> 1);
-        }
     }
 
     // BwdTrans along xi_0: lane (i1, i2)
@@ -765,7 +734,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     // apply kernels: the first faces' per-point data in flight during the line phases
     FaceU<R> fu0, fu1;
     FaceD<R> fd0, fd1;
-    if (MODE != 0) {
+    {
         fu0 = face_uniform<R>(meta, 0);
         fd0 = load_face<R, P, MODE>(D, fu0, 0);
         fu1 = face_uniform<R>(meta, 1);
@@ -817,7 +786,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     }
     __syncthreads();
     R z_u[2], z_dk[2], z_da[2], z_db[2];   // faces normal to xi_2 at (q0, q1) = (a, b)
-    if (MODE != 0 && col) {
+    if (col) {
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             d0[q] = SA[pa<P>(a, b, q)];
@@ -840,21 +809,6 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     }
     __syncthreads();
 
-    if (MODE == 0) {
-        {
-            R vA[4] = {z_u[0], z_dk[0], z_da[0], z_db[0]}, vB[4] = {z_u[1], z_dk[1], z_da[1], z_db[1]};
-            face_store2<R, P>(D, itl, tu[4], td[4], vA, tu[5], td[5], vB, SA);
-        }
-        {
-            R vA[4] = {x_u[0], x_dk[0], x_da[0], x_db[0]}, vB[4] = {x_u[1], x_dk[1], x_da[1], x_db[1]};
-            face_store2<R, P>(D, itl, tu[0], td[0], vA, tu[1], td[1], vB, SA);
-        }
-        {
-            R vA[4] = {y_u[0], y_dk[0], y_da[0], y_db[0]}, vB[4] = {y_u[1], y_dk[1], y_da[1], y_db[1]};
-            face_store2<R, P>(D, itl, tu[2], td[2], vA, tu[3], td[3], vB, SA);
-        }
-        return;
-    }
 
     if constexpr (MODE == 1) {
     // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
@@ -1127,9 +1081,210 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     }
 }
 
+// ---------------------------------------------------------------------------
+// Trace kernel by face reductions (the element's own trace evaluation, eq.
+// TracePhysEval of Sec. 3.2): for the two faces normal to xi_k, lane (ia, ib)
+// reduces the coefficients along xi_k against P_i(+-1) and P'_i(+-1); two 1-D
+// contractions with P_i, P'_i at the face's n_F GLL trace points then give u
+// and grad_xi u there directly.  u is a polynomial of degree p in each
+// direction, so this equals interpolating the face values at the p + 2 GLL
+// points to the trace (up to rounding), without the volume transform.
+//
+// LDS (R units): the coefficients [NP^3], the reductions of one direction
+// [4][W], the first contractions of its two faces [2 sides][3][W], and the
+// trace tables P_i(z_t), P'_i(z_t), t < m, i < NP for m = n .. NFMAX.
+template <int P>
+struct TSz {
+    static constexpr int NP = P + 1, N = P + 2, W = Geo<P>::W, M = Geo<P>::NFMAX;
+    static constexpr int XS = (NP * NP * NP + 1) & ~1;
+    static constexpr int NU = 4 * W, NW = 6 * W;
+    // table set of m trace points: BF [m][NP] then DBF [m][NP]
+    static constexpr int bt_off(int m) { return NP * ((m - 1) * m - (N - 1) * N); }
+    static constexpr int BT = bt_off(M + 1);
+    static constexpr int TOTAL = XS + NU + NW + BT;
+};
+
+template <class R, int P>
+__device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
+    using T = TSz<P>;
+    constexpr int NP = T::NP, N = T::N, WG = T::W, SG = Geo<P>::S, NM = NP * NP * NP;
+    R *XS = reinterpret_cast<R *>(smem_raw);
+    R *NU = XS + T::XS;
+    R *NW = NU + T::NU;
+    R *BT = NW + T::NW;
+    const ElemDesc ed = A.desc[blk];
+    const int l = threadIdx.x, a = gx<P>(l), b = gy<P>(l);
+    const bool ln = a < NP && b < NP;
+    const MetaV<R> meta = load_meta<R, 0>(A, D, blk);
+    // the coefficients (coalesced) and the trace tables into LDS: every load
+    // issued before the first store
+    constexpr int XIT = (NM + WG - 1) / WG, BIT = (T::BT / 2 + WG - 1) / WG;
+    R xv[XIT], bv[2 * BIT];
+    {
+        const R *__restrict__ xe = D.x + ed.xoff;
+#pragma unroll
+        for (int it = 0; it < XIT; ++it) {
+            const int i = l + it * WG;
+            xv[it] = (it + 1) * WG <= NM || i < NM ? xe[i < NM ? i : 0] : R(0);
+        }
+    }
+    // table entry i of the BF half: set m, row t, mode j (the DBF entry follows the row set)
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+        const int i = l + it * WG;
+        int m = N, r = i;
+#pragma unroll
+        for (int mm = N; mm < T::M; ++mm)
+            if (r >= m * NP) {
+                r -= m * NP;
+                ++m;
+            }
+        const int t = r / NP, j = r - t * NP;
+        const bool ok = i < T::BT / 2;
+        bv[2 * it] = ok ? D.tab[tab_off_BF(m) + t * S9 + j] : R(0);
+        bv[2 * it + 1] = ok ? D.tab[tab_off_DBF(m) + t * S9 + j] : R(0);
+    }
+    // every face's per-point data in flight meanwhile
+    FaceU<R> tu[6];
+    FaceD<R> td[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        tu[f] = face_uniform<R>(meta, f);
+        td[f] = load_face<R, P, 0>(D, tu[f], f >> 1);
+    }
+#pragma unroll
+    for (int it = 0; it < XIT; ++it)
+        if ((it + 1) * WG <= NM || l + it * WG < NM) XS[l + it * WG] = xv[it];
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+        const int i = l + it * WG;
+        if (i < T::BT / 2) {
+            int m = N, r = i;
+#pragma unroll
+            for (int mm = N; mm < T::M; ++mm)
+                if (r >= m * NP) {
+                    r -= m * NP;
+                    ++m;
+                }
+            BT[T::bt_off(m) + r] = bv[2 * it];
+            BT[T::bt_off(m) + m * NP + r] = bv[2 * it + 1];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // reductions along xi_k at xi_k = -1 (r0: u, r1: d_k u) and +1 (r2, r3)
+        R r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+        if (ln) {
+#pragma unroll
+            for (int ik = 0; ik < NP; ++ik) {
+                const int idx = k == 0 ? ik + NP * (a + NP * b) : (k == 1 ? a + NP * (ik + NP * b) : a + NP * (b + NP * ik));
+                const R xv = XS[idx];
+                const R dv = R(0.5 * ik * (ik + 1));
+                const R sx = (ik & 1) ? -xv : xv;
+                r0 += sx;
+                r1 -= dv * sx;
+                r2 += xv;
+                r3 += dv * xv;
+            }
+        }
+        NU[l] = r0;
+        NU[WG + l] = r1;
+        NU[2 * WG + l] = r2;
+        NU[3 * WG + l] = r3;
+        __syncthreads();
+        // first contraction, along the face direction a: lane (t1, ib)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const FaceU<R> &fu = tu[2 * k + s];
+            if (a < fu.nf && b < NP) {
+                const R *bf = BT + T::bt_off(fu.nf) + NP * a, *dbf = bf + fu.nf * NP;
+                const R *u0 = NU + 2 * s * WG + SG * b, *u1 = u0 + WG;
+                R w0 = 0, w0d = 0, w1 = 0;
+#pragma unroll
+                for (int ia = 0; ia < NP; ++ia) {
+                    const R x0 = u0[ia];
+                    w0 += bf[ia] * x0;
+                    w0d += dbf[ia] * x0;
+                    w1 += bf[ia] * u1[ia];
+                }
+                NW[3 * s * WG + l] = w0;
+                NW[(3 * s + 1) * WG + l] = w0d;
+                NW[(3 * s + 2) * WG + l] = w1;
+            }
+        }
+        __syncthreads();
+        // second contraction, along b: lane (t1, t2); g = C . grad_xi u; store
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const FaceU<R> &fu = tu[2 * k + s];
+            const FaceD<R> &fd = td[2 * k + s];
+            if (a < fu.nf && b < fu.nf) {
+                const R *bf = BT + T::bt_off(fu.nf) + NP * b, *dbf = bf + fu.nf * NP;
+                const R *w0 = NW + 3 * s * WG + a, *w0d = w0 + WG, *w1 = w0 + 2 * WG;
+                R vu = 0, vda = 0, vdb = 0, vdk = 0;
+#pragma unroll
+                for (int ib = 0; ib < NP; ++ib) {
+                    const R bv = bf[ib], x0 = w0[SG * ib];
+                    vu += bv * x0;
+                    vda += bv * w0d[SG * ib];
+                    vdb += dbf[ib] * x0;
+                    vdk += bv * w1[SG * ib];
+                }
+                R *__restrict__ tb = D.tbuf + fu.to + tb_side(fu.slot) * 2 * fu.npf + fd.qc;
+                tb[0] = vu;
+                tb[fu.npf] = fd.Ck * vdk + fd.Ca * vda + fd.Cb * vdb;
+            }
+        }
+    }
+}
+
+template <class R, int P>
+__global__ __launch_bounds__(Geo<P>::W) void k3t(Args A, Data<R> D) {
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    k3t_elem<R, P>(A, D, blockIdx.x, smem_raw);
+}
+
+// Trace stage of every element of order <= 6 (traces <= 8 x 8) in one launch:
+// block b takes element b of A.desc / A.fdesc, its order in ElemDesc::pad.
+template <class R>
+__global__ __launch_bounds__(W) void k3t_all(Args A, Data<R> D) {
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int i = blockIdx.x;
+    switch (A.desc[i].pad) {
+    case 1: k3t_elem<R, 1>(A, D, i, smem_raw); break;
+    case 2: k3t_elem<R, 2>(A, D, i, smem_raw); break;
+    case 3: k3t_elem<R, 3>(A, D, i, smem_raw); break;
+    case 4: k3t_elem<R, 4>(A, D, i, smem_raw); break;
+    case 5: k3t_elem<R, 5>(A, D, i, smem_raw); break;
+    default: k3t_elem<R, 6>(A, D, i, smem_raw); break;
+    }
+}
+__host__ __device__ constexpr int lds_trace_all() {
+    int m = 0;
+    const int v[6] = {TSz<1>::TOTAL, TSz<2>::TOTAL, TSz<3>::TOTAL, TSz<4>::TOTAL, TSz<5>::TOTAL, TSz<6>::TOTAL};
+    for (int i = 0; i < 6; ++i) m = v[i] > m ? v[i] : m;
+    return m;
+}
+
+// LDS (R units) of a launch: the trace kernel (mode 0) or the apply kernels
+template <int P>
+__host__ __device__ constexpr int lds_mode(int mode) {
+    return mode == 0 ? TSz<P>::TOTAL : lds_total<P>(mode);
+}
+
+// Waves per SIMD the compiler sizes the registers of a kernel for.
+template <class R, int P, int MODE>
+struct Occ {
+    static constexpr int V = 2;
+};
+
 // One launch per order group: block b handles element b of the group.
 template <class R, int P, int MODE>
-__global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(2))) void k3g(Args A, Data<R> D) {
+__global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(Occ<R, P, MODE>::V))) void k3g(Args A,
+                                                                                                         Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     k3g_elem<R, P, MODE>(A, D, blockIdx.x, smem_raw);
@@ -1139,10 +1294,16 @@ __global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(2))) 
 template <int MODE>
 __host__ __device__ constexpr int lds_persistent() {
     int m = 0;
-    const int v[6] = {lds_total<1>(MODE), lds_total<2>(MODE), lds_total<3>(MODE),
-                      lds_total<4>(MODE), lds_total<5>(MODE), lds_total<6>(MODE)};
+    const int v[6] = {lds_mode<1>(MODE), lds_mode<2>(MODE), lds_mode<3>(MODE),
+                      lds_mode<4>(MODE), lds_mode<5>(MODE), lds_mode<6>(MODE)};
     for (int i = 0; i < 6; ++i) m = v[i] > m ? v[i] : m;
     return m;
+}
+
+template <class R, int P, int MODE>
+__device__ __forceinline__ void gf_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
+    if constexpr (MODE == 0) k3t_elem<R, P>(A, D, blk, smem_raw);
+    else k3g_elem<R, P, MODE>(A, D, blk, smem_raw);
 }
 
 // One persistent launch for elements of every order <= 6: A.desc / A.fdesc
@@ -1155,12 +1316,12 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
     for (int i = blockIdx.x; i < A.count; i += gridDim.x) {
         const int P = A.desc[i].pad;
         switch (P) {
-        case 1: k3g_elem<R, 1, MODE>(A, D, i, smem_raw); break;
-        case 2: k3g_elem<R, 2, MODE>(A, D, i, smem_raw); break;
-        case 3: k3g_elem<R, 3, MODE>(A, D, i, smem_raw); break;
-        case 4: k3g_elem<R, 4, MODE>(A, D, i, smem_raw); break;
-        case 5: k3g_elem<R, 5, MODE>(A, D, i, smem_raw); break;
-        default: k3g_elem<R, 6, MODE>(A, D, i, smem_raw); break;
+        case 1: gf_elem<R, 1, MODE>(A, D, i, smem_raw); break;
+        case 2: gf_elem<R, 2, MODE>(A, D, i, smem_raw); break;
+        case 3: gf_elem<R, 3, MODE>(A, D, i, smem_raw); break;
+        case 4: gf_elem<R, 4, MODE>(A, D, i, smem_raw); break;
+        case 5: gf_elem<R, 5, MODE>(A, D, i, smem_raw); break;
+        default: gf_elem<R, 6, MODE>(A, D, i, smem_raw); break;
         }
         __syncthreads();   // the next element reuses the LDS
     }

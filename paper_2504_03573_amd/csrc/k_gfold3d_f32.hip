@@ -7,6 +7,8 @@ template <class R>
 hipError_t launch_gfold3d(int P, int mode, int nfmax, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 template <class R>
 hipError_t launch_gfold3d_persistent(int mode, int grid, const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
+template <class R>
+hipError_t launch_gfold3d_trace_all(const g3::Args &A, const g3::Data<R> &D, hipStream_t st);
 
 namespace {
 template <int P>
@@ -14,9 +16,9 @@ hipError_t gfold_p(int mode, int nfmax, const g3::Args &A, const g3::Data<float>
     // the lane grid covers traces up to NFMAX x NFMAX points
     if (nfmax > g3::Geo<P>::NFMAX) return hipErrorInvalidValue;
     if (A.count <= 0) return hipSuccess;
-    const size_t lds = sizeof(float) * g3::lds_total<P>(mode);
+    const size_t lds = sizeof(float) * g3::lds_mode<P>(mode);
     const dim3 blk(g3::Geo<P>::W);
-    if (mode == 0) hipLaunchKernelGGL((g3::k3g<float, P, 0>), dim3(A.count), blk, lds, st, A, D);
+    if (mode == 0) hipLaunchKernelGGL((g3::k3t<float, P>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 1) hipLaunchKernelGGL((g3::k3g<float, P, 1>), dim3(A.count), blk, lds, st, A, D);
     else if constexpr (P <= 6) hipLaunchKernelGGL((g3::k3g<float, P, 2>), dim3(A.count), blk, lds, st, A, D);
     else return hipErrorInvalidValue;   // the fused kernel covers orders <= 6
@@ -51,6 +53,14 @@ hipError_t launch_gfold3d_persistent<float>(int mode, int grid, const g3::Args &
         const size_t lds = sizeof(float) * g3::lds_persistent<1>();
         hipLaunchKernelGGL((g3::k3g_persistent<float, 1>), dim3(grid), dim3(g3::W), lds, st, A, D);
     }
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_gfold3d_trace_all<float>(const g3::Args &A, const g3::Data<float> &D, hipStream_t st) {
+    if (A.count <= 0) return hipSuccess;
+    const size_t lds = sizeof(float) * g3::lds_trace_all();
+    hipLaunchKernelGGL((g3::k3t_all<float>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     return hipGetLastError();
 }
 

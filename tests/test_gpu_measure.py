@@ -49,10 +49,18 @@ def test_apply_timed(P, variant):
             if dt == torch.float64:
                 assert torch.equal(y, y_ref)
             continue
-        assert len(launches) == 2 * groups
-        assert [L["stage"] for L in launches] == [1] * groups + [2] * groups
-        assert sorted(L["order"] for L in launches[groups:]) == sorted(set(m.order.tolist()))
-        assert sum(L["elements"] for L in launches[groups:]) == m.n_elems
+        if variant == "gather_fold":
+            # orders <= 6: one trace launch for every order, then one apply per order
+            assert [(L["stage"], L["order"], L["elements"]) for L in launches[:1]] == [(1, 0, m.n_elems)]
+            launches_t = launches[:1]
+        else:
+            launches_t = launches[:groups]
+            assert [L["stage"] for L in launches_t] == [1] * groups
+        nt = len(launches_t)
+        assert len(launches) == nt + groups
+        assert [L["stage"] for L in launches[nt:]] == [2] * groups
+        assert sorted(L["order"] for L in launches[nt:]) == sorted(set(m.order.tolist()))
+        assert sum(L["elements"] for L in launches[nt:]) == m.n_elems
         assert all(L["ms"] > 0 for L in launches)
         assert sum(L["alg_bytes"] for L in launches) == pytest.approx(_alg_bytes(st, 3, word), rel=1e-12)
         if dt == torch.float64:
