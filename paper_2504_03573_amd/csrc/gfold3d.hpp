@@ -73,7 +73,15 @@ struct Sz {
     static_assert(S1 >= N && S2 >= S1 * (N - 1) + N, "point arrays must not overlap");
     static constexpr int ARR = S2 * N;          // one padded point array
     static constexpr int SCR = 24 * Geo<P>::W;  // face scratch, aliases the point arrays
-    static constexpr int TOTAL = 2 * ARR > SCR ? 2 * ARR : SCR;
+    // Every trace of this order has the element's own n points (n = NFMAX):
+    // the apply takes its own (u, g) from its face values instead of the trace
+    // buffer, and keeps the fields of the faces normal to xi_1 and xi_2 until
+    // their phase in OWN_STASH = [16][W] after the point arrays (each lane
+    // reads back only its own entries; the face scratch beyond FB is unused,
+    // since no face interpolates).
+    static constexpr bool OWN = N == Geo<P>::NFMAX;
+    static constexpr int STASH = OWN ? 16 * Geo<P>::W : 0;
+    static constexpr int TOTAL = 2 * ARR + STASH > SCR ? 2 * ARR + STASH : SCR;
 };
 
 // face scratch (R units from the block's LDS base, W = Geo<P>::W):
@@ -294,8 +302,10 @@ __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &
     if (MODE == 1) {
         const R *__restrict__ tb = D.tbuf + u.to + d.qc;
         const int so = tb_side(u.slot);
-        d.ou = tb[so * 2 * npf];
-        d.og = tb[so * 2 * npf + npf];
+        if constexpr (!Sz<P>::OWN) {
+            d.ou = tb[so * 2 * npf];
+            d.og = tb[so * 2 * npf + npf];
+        }
         if (u.slot != 2) {
             d.n0 = tb[(1 - so) * 2 * npf];
             d.n1 = tb[(1 - so) * 2 * npf + npf];
@@ -464,6 +474,19 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
         for (int f = 0; f < 4; ++f) LB[f] = c[f];
     }
     __syncthreads();
+}
+
+// Own (u, g) of the two faces of one direction from this lane's stashed
+// fields (u, d_k u, d_a u, d_b u of each face, from entry f0 on): g = C . grad_xi u.
+template <class R, int P>
+__device__ __forceinline__ void own_from_stash(const R *OS, int f0, FaceD<R> &dA, FaceD<R> &dB) {
+    constexpr int ws = Geo<P>::W;
+    const int l = threadIdx.x;
+    const R *o = OS + f0 * ws + l;
+    dA.ou = o[0];
+    dA.og = dA.Ck * o[ws] + dA.Ca * o[2 * ws] + dA.Cb * o[3 * ws];
+    dB.ou = o[4 * ws];
+    dB.og = dB.Ck * o[5 * ws] + dB.Ca * o[6 * ws] + dB.Cb * o[7 * ws];
 }
 
 // Flux of eq. IP at this lane's trace point from both sides' (u, g) in the
@@ -807,6 +830,20 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
         z_db[0] = SB[pa<P>(a, b, 0)];
         z_db[1] = SB[pa<P>(a, b, N - 1)];
     }
+    R *OS = SA + 2 * S::ARR;   // own-field stash (S::OWN)
+    if constexpr (MODE == 1 && S::OWN) {
+        // own (u, g) of the faces normal to xi_0 now; the others' fields kept
+        fd0.ou = x_u[0];
+        fd0.og = fd0.Ck * x_dk[0] + fd0.Ca * x_da[0] + fd0.Cb * x_db[0];
+        fd1.ou = x_u[1];
+        fd1.og = fd1.Ck * x_dk[1] + fd1.Ca * x_da[1] + fd1.Cb * x_db[1];
+        if (col) {
+            const R st[16] = {y_u[0], y_dk[0], y_da[0], y_db[0], y_u[1], y_dk[1], y_da[1], y_db[1],
+                              z_u[0], z_dk[0], z_da[0], z_db[0], z_u[1], z_dk[1], z_da[1], z_db[1]};
+#pragma unroll
+            for (int f = 0; f < 16; ++f) OS[f * WG + l] = st[f];
+        }
+    }
     __syncthreads();
 
 
@@ -839,9 +876,9 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
             flux_tb<R, P>(fu0, fd0, LA);
             flux_tb<R, P>(fu1, fd1, LB);
             const FaceU<R> fu2 = face_uniform<R>(meta, 2);
-            const FaceD<R> fd2 = load_face<R, P, MODE>(D, fu2, 1);
+            FaceD<R> fd2 = load_face<R, P, MODE>(D, fu2, 1);
             const FaceU<R> fu3 = face_uniform<R>(meta, 3);
-            const FaceD<R> fd3 = load_face<R, P, MODE>(D, fu3, 1);
+            FaceD<R> fd3 = load_face<R, P, MODE>(D, fu3, 1);
             lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 8 * WG, LA, LB);
 #pragma unroll
             for (int f = 0; f < 4; ++f) {
@@ -861,6 +898,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
             }
             __syncthreads();
             // normal to xi_1: own points (q0, q2) on column lanes q1 = 0, n-1
+            if constexpr (S::OWN) own_from_stash<R, P>(OS, 0, fd2, fd3);
             flux_tb<R, P>(fu2, fd2, LA);
             flux_tb<R, P>(fu3, fd3, LB);
             fu0 = face_uniform<R>(meta, 4);
@@ -886,6 +924,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
             }
             __syncthreads();
             // normal to xi_2: own points (q0, q1) are the column ends
+            if constexpr (S::OWN) own_from_stash<R, P>(OS, 8, fd0, fd1);
             flux_tb<R, P>(fu0, fd0, LA);
             flux_tb<R, P>(fu1, fd1, LB);
             lift2<R, P>(itl, fu0.nf, fu1.nf, SA + 8 * WG, LA, LB);
