@@ -97,7 +97,8 @@ static int ensure_cg(sipdg_ctx *c) {
     w->V.done = w->d_done;
     const int np = c->nprob;
     ALLOC(w->d_sc, 5 * np + 1);
-    ALLOC(w->d_si, 2 * np + 2);
+    ALLOC(w->d_si, 2 * np + 4);
+    HIPCHK(hipMemset(w->d_si, 0, sizeof(int) * (2 * np + 4)));
     w->S.rho = w->d_sc;
     w->S.alpha = w->d_sc + np;
     w->S.beta = w->d_sc + 2 * np;
@@ -108,6 +109,8 @@ static int ensure_cg(sipdg_ctx *c) {
     w->S.iters = w->d_si + np;
     w->S.counter = w->d_si + 2 * np;
     w->S.flags = w->d_si + 2 * np + 1;
+    w->S.nact = w->d_si + 2 * np + 2;
+    w->S.nfin = w->d_si + 2 * np + 3;
     ALLOC(w->p1, nblk);
     ALLOC(w->p2, nblk);
     const int64_t n = c->ndof;

@@ -28,6 +28,7 @@ struct CgScalars {
     int *counter;   // [1] iterations executed by the whole batch
     int *flags;     // [1] bit 1: breakdown seen
     double *tol;    // [1] relative tolerance of the running solve (set by the start kernel)
+    int *nact, *nfin;   // [1] each: vote counters of the finalisation launches (zero between launches)
 };
 
 template <class R>

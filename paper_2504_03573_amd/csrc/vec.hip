@@ -71,57 +71,79 @@ __global__ __launch_bounds__(VB) void k_pupdate(VecCtx V, const CgScalars S, con
     for (int64_t i = s + threadIdx.x; i < e; i += VB) p[i] = (R)((double)z[i] + beta * (double)p[i]);
 }
 
+// Sum of part[b0, b1) by the whole block in a fixed order: thread t adds
+// b0 + t, b0 + t + VB, ..., then the fixed tree of block_sum.
+__device__ inline double seg_sum(const double *part, int b0, int b1, double *red) {
+    double acc = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += VB) acc += part[b];
+    return block_sum(acc, red);
+}
+
+// Batch-wide vote of the per-problem blocks of a finalisation launch (thread
+// 0 of each block): the block that finishes last gets true and the number of
+// active problems, and zeroes both counters for the next launch.
+__device__ inline bool last_vote(int *nact, int *nfin, bool active, int &total) {
+    if (active) atomicAdd(nact, 1);
+    __threadfence();
+    if (atomicAdd(nfin, 1) != (int)gridDim.x - 1) return false;
+    __threadfence();
+    total = atomicExch(nact, 0);
+    atomicExch(nfin, 0);
+    return true;
+}
+
 // alpha = rho / p.q per problem (0 once converged); breakdown if p.q <= 0.
-__global__ void k_fin_alpha(VecCtx V, CgScalars S, const double *ppq) {
+// One block per problem.
+__global__ __launch_bounds__(VB) void k_fin_alpha(VecCtx V, CgScalars S, const double *ppq) {
     if (V.done && *V.done) return;
-    for (int p = threadIdx.x; p < V.nprob; p += blockDim.x) {
-        double pq = 0.0;
-        for (int b = V.prob_blk[p]; b < V.prob_blk[p + 1]; ++b) pq += ppq[b];
-        if (S.conv[p]) {
-            S.alpha[p] = 0.0;
-        } else if (!(pq > 0.0)) {
-            S.alpha[p] = 0.0;
-            S.conv[p] = 2;   // breakdown
-            atomicOr(S.flags, 2);
-        } else {
-            S.alpha[p] = S.rho[p] / pq;
-        }
+    __shared__ double red[VB];
+    const int p = blockIdx.x;
+    const double pq = seg_sum(ppq, V.prob_blk[p], V.prob_blk[p + 1], red);
+    if (threadIdx.x != 0) return;
+    if (S.conv[p]) {
+        S.alpha[p] = 0.0;
+    } else if (!(pq > 0.0)) {
+        S.alpha[p] = 0.0;
+        S.conv[p] = 2;   // breakdown
+        atomicOr(S.flags, 2);
+    } else {
+        S.alpha[p] = S.rho[p] / pq;
     }
 }
 
-// residual test and beta per problem; sets *done when every problem stopped.
-__global__ void k_fin_beta(VecCtx V, CgScalars S, const double *prr, const double *prz) {
+// residual test and beta per problem (one block each); the last block sets
+// *done when every problem has stopped.
+__global__ __launch_bounds__(VB) void k_fin_beta(VecCtx V, CgScalars S, const double *prr, const double *prz) {
     if (V.done && *V.done) return;
-    const double tol = S.tol[0];
-    __shared__ int active;
-    if (threadIdx.x == 0) active = 0;
-    __syncthreads();
-    for (int p = threadIdx.x; p < V.nprob; p += blockDim.x) {
-        if (S.conv[p]) {
-            S.beta[p] = 0.0;
-            continue;
-        }
-        double rr = 0.0, rz = 0.0;
-        for (int b = V.prob_blk[p]; b < V.prob_blk[p + 1]; ++b) {
-            rr += prr[b];
-            rz += prz[b];
-        }
+    __shared__ double red[VB];
+    const int p = blockIdx.x;
+    const bool run = S.conv[p] == 0;   // the same on every thread
+    double rr = 0.0, rz = 0.0;
+    if (run) {
+        rr = seg_sum(prr, V.prob_blk[p], V.prob_blk[p + 1], red);
+        rz = seg_sum(prz, V.prob_blk[p], V.prob_blk[p + 1], red);
+    }
+    if (threadIdx.x != 0) return;
+    bool active = false;
+    if (!run) {
+        S.beta[p] = 0.0;
+    } else {
         S.iters[p] += 1;
         const double rel = sqrt(rr) / S.bnorm[p];
         S.rel[p] = rel;
-        if (rel <= tol || !(S.bnorm[p] > 0.0)) {
+        if (rel <= S.tol[0] || !(S.bnorm[p] > 0.0)) {
             S.conv[p] = 1;
             S.beta[p] = 0.0;
         } else {
             S.beta[p] = rz / S.rho[p];
             S.rho[p] = rz;
-            atomicAdd(&active, 1);
+            active = true;
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    int total = 0;
+    if (last_vote(S.nact, S.nfin, active, total)) {
         S.counter[0] += 1;
-        if (active == 0) *V.done = 1;
+        if (total == 0) *V.done = 1;
     }
 }
 
@@ -150,45 +172,39 @@ __global__ __launch_bounds__(VB) void k_start(VecCtx V, const R *r, const R *din
     }
 }
 
-// rho = r.z, bnorm given by bnorm_src (or ||r|| when null), conv = (||r|| <= tol bnorm)
-__global__ void k_fin_start(VecCtx V, CgScalars S, const double *prr, const double *prz,
-                            const double *bnorm_src, const int *preconv, double tol) {
-    __shared__ int active;
-    if (threadIdx.x == 0) active = 0;
-    __syncthreads();
-    for (int p = threadIdx.x; p < V.nprob; p += blockDim.x) {
-        double rr = 0.0, rz = 0.0;
-        for (int b = V.prob_blk[p]; b < V.prob_blk[p + 1]; ++b) {
-            rr += prr[b];
-            rz += prz[b];
-        }
-        const double bn = bnorm_src ? bnorm_src[p] : sqrt(rr);
-        S.bnorm[p] = bn;
-        S.rho[p] = rz;
-        S.alpha[p] = 0.0;
-        S.beta[p] = 0.0;
-        S.iters[p] = 0;
-        S.rel[p] = bn > 0.0 ? sqrt(rr) / bn : 0.0;
-        const bool c = (preconv && preconv[p]) || !(bn > 0.0) || sqrt(rr) <= tol * bn;
-        S.conv[p] = c ? 1 : 0;
-        if (!c) atomicAdd(&active, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *V.done = active == 0 ? 1 : 0;
+// rho = r.z, bnorm given by bnorm_src (or ||r|| when null), conv = (||r|| <= tol bnorm);
+// one block per problem, the last one sets *done and the batch counters.
+__global__ __launch_bounds__(VB) void k_fin_start(VecCtx V, CgScalars S, const double *prr, const double *prz,
+                                                   const double *bnorm_src, const int *preconv, double tol) {
+    __shared__ double red[VB];
+    const int p = blockIdx.x;
+    const double rr = seg_sum(prr, V.prob_blk[p], V.prob_blk[p + 1], red);
+    const double rz = seg_sum(prz, V.prob_blk[p], V.prob_blk[p + 1], red);
+    if (threadIdx.x != 0) return;
+    const double bn = bnorm_src ? bnorm_src[p] : sqrt(rr);
+    S.bnorm[p] = bn;
+    S.rho[p] = rz;
+    S.alpha[p] = 0.0;
+    S.beta[p] = 0.0;
+    S.iters[p] = 0;
+    S.rel[p] = bn > 0.0 ? sqrt(rr) / bn : 0.0;
+    const bool c = (preconv && preconv[p]) || !(bn > 0.0) || sqrt(rr) <= tol * bn;
+    S.conv[p] = c ? 1 : 0;
+    int total = 0;
+    if (last_vote(S.nact, S.nfin, !c, total)) {
+        *V.done = total == 0 ? 1 : 0;
         S.counter[0] = 0;
         S.flags[0] = 0;
         S.tol[0] = tol;
     }
 }
 
-// out_p = sqrt(sum of partials) per problem
-__global__ void k_fin_norm(VecCtx V, const double *part, double *out) {
-    for (int p = threadIdx.x; p < V.nprob; p += blockDim.x) {
-        double s = 0.0;
-        for (int b = V.prob_blk[p]; b < V.prob_blk[p + 1]; ++b) s += part[b];
-        out[p] = sqrt(s);
-    }
+// out_p = sqrt(sum of partials) per problem (one block each)
+__global__ __launch_bounds__(VB) void k_fin_norm(VecCtx V, const double *part, double *out) {
+    __shared__ double red[VB];
+    const int p = blockIdx.x;
+    const double s = seg_sum(part, V.prob_blk[p], V.prob_blk[p + 1], red);
+    if (threadIdx.x == 0) out[p] = sqrt(s);
 }
 
 // r = b - q  (FP64) with partials of r.r
@@ -261,20 +277,20 @@ hipError_t vec_fill(R *v, int64_t n, R val, hipStream_t st) {
     LCHK();
 }
 hipError_t vec_fin_alpha(const VecCtx &V, const CgScalars &S, const double *ppq, hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(64), 0, st, V, S, ppq);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(V.nprob), dim3(VB), 0, st, V, S, ppq);
     LCHK();
 }
 hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz, hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(64), 0, st, V, S, prr, prz);
+    hipLaunchKernelGGL(k_fin_beta, dim3(V.nprob), dim3(VB), 0, st, V, S, prr, prz);
     LCHK();
 }
 hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
                          const double *bnorm_src, const int *preconv, double tol, hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(64), 0, st, V, S, prr, prz, bnorm_src, preconv, tol);
+    hipLaunchKernelGGL(k_fin_start, dim3(V.nprob), dim3(VB), 0, st, V, S, prr, prz, bnorm_src, preconv, tol);
     LCHK();
 }
 hipError_t vec_fin_norm(const VecCtx &V, const double *part, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_norm, dim3(1), dim3(64), 0, st, V, part, out);
+    hipLaunchKernelGGL(k_fin_norm, dim3(V.nprob), dim3(VB), 0, st, V, part, out);
     LCHK();
 }
 hipError_t vec_resid(const VecCtx &V, const double *b, const double *q, double *r, double *prr,
