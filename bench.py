@@ -132,12 +132,38 @@ def cpu_baseline(mesh, x, budget_s=12.0):
     om.apply(x, elems=sel)
     dt = time.perf_counter() - t0
     nd = int(dofs[sel].sum())
+    threads = oracle.num_threads()
+    # the same oracle on one thread, a smaller sample of the same rows
+    k1 = max(16, min(k2, int(k2 * 0.25 / threads) + 1))
+    sel1 = np.sort(perm[:k1])
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        om.apply(x, elems=sel1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    nd1 = int(dofs[sel1].sum())
     return {
-        "value": nd / dt / 1e9, "unit": "GDOF/s", "cores": oracle.num_threads(), "kind": "oracle",
+        "value": nd / dt / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
         "sample": f"rows of {k2} of {mesh.n_elems} elements ({nd} of {int(dofs.sum())} DOFs), "
                   f"{dt:.1f} s, plain FP64 oracle, OpenMP over elements",
         "seconds": dt,
+        "one_thread": {"value": nd1 / dt1 / 1e9, "unit": "GDOF/s", "seconds": dt1,
+                       "sample": f"rows of {k1} elements ({nd1} DOFs)"},
+        "host_cpu": _cpu_model(),
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -149,6 +175,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="kept for the profiling commands (the 1 GiB copy always runs)")
+    ap.add_argument("--variant", default=None,
+                    help="kernel structure to use instead of the autotuner's choice (profiling runs)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_hex32_p3to6.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -166,6 +194,9 @@ def main():
     st = inspect_mesh(mesh)
     op = SipdgOperator(mesh)
     tuned = op.autotune(20)
+    if args.variant:
+        # profiling runs pin the kernel structure (counters distort the autotuner's timing)
+        op.variant = args.variant
     stream = torch.cuda.current_stream()
     x_np = synth.random_coefficients(mesh, 4000 + WORKLOAD)
     x = torch.tensor(x_np, device="cuda")

@@ -81,9 +81,10 @@ def _load():
         lib.oracle_min_detj.argtypes = [P, vp]
         lib.oracle_face_moments.argtypes = [P, vp, vp]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         for f in (lib.oracle_apply, lib.oracle_diagonal, lib.oracle_points, lib.oracle_rhs,
                   lib.oracle_param_grad, lib.oracle_sample, lib.oracle_min_detj,
-                  lib.oracle_face_moments, lib.oracle_num_threads):
+                  lib.oracle_face_moments, lib.oracle_num_threads, lib.oracle_set_num_threads):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -91,6 +92,11 @@ def _load():
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops from now on; returns the new count."""
+    return int(_load().oracle_set_num_threads(int(n)))
 
 
 # ---------------------------------------------------------------- quadrature

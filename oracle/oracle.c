@@ -653,3 +653,15 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of threads of the OpenMP loops (n >= 1); returns the new count. */
+int oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
