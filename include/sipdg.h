@@ -249,7 +249,7 @@ typedef struct {
                           residual still needs, max(inner_tol, tol ||b|| / (2 ||r||)) */
     int precond;       /* 1 = Jacobi, 0 = none */
     int graph_k;       /* iterations per captured HIP graph / per host check; 0 = no graph */
-    int max_outer;     /* F32_IR: max refinement steps (50) */
+    int max_outer;     /* F32_IR: max refinement steps; F64: max restarts from the true residual, plus one (50) */
     /* optional checkpoint: called every checkpoint_every iterations with the
      * device pointers of the FP64 iterate x and residual r and the iteration
      * count; x0_given = 1 starts from the x passed in (resume). */
@@ -261,7 +261,7 @@ typedef struct {
 
 typedef struct {
     int iters;              /* total (inner) iterations */
-    int outer_iters;        /* refinement steps (F32_IR), 1 for F64 */
+    int outer_iters;        /* refinement steps (F32_IR); F64: 1 + restarts from the true residual */
     int converged;          /* all problems met tol */
     double rel_resid;       /* max over problems of true ||b-Ax||/||b|| (FP64) */
     double time_ms;         /* wall time of the solve */

@@ -817,11 +817,23 @@ int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *d
         HIPCHK(hipMalloc((void **)&h->d_face_tmp, sizeof(double) * std::max<int64_t>(1, h->nfaces)));
         HIPCHK(hipMalloc((void **)&h->d_elem_tmp, sizeof(double) * std::max<int64_t>(1, h->ne)));
     }
+    // traces of a and b: the trace stage of the handle's kernel structure
+    // (every structure but the fused ones has one), else the general kernels
+    const bool fused = h->variant == SIPDG_VARIANT_FUSED || h->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED;
+    if (!fused) {
+        int rc = apply_impl<double>(h, a, nullptr, h->d_tbuf, nullptr, st, 1);
+        if (rc) return rc;
+        rc = apply_impl<double>(h, b, nullptr, h->d_tbuf2, nullptr, st, 1);
+        if (rc) return rc;
+    }
     for (const Group &g : h->groups) {
-        OpArgs<double> A = make_args<double>(h, g, a, nullptr, h->d_tbuf, nullptr);
-        HIPCHK(launch_op<double>(h->dim, g.P, OP_TRACE, A, g.nfmax, st));
-        A = make_args<double>(h, g, b, nullptr, h->d_tbuf2, nullptr);
-        HIPCHK(launch_op<double>(h->dim, g.P, OP_TRACE, A, g.nfmax, st));
+        OpArgs<double> A;
+        if (fused) {
+            A = make_args<double>(h, g, a, nullptr, h->d_tbuf, nullptr);
+            HIPCHK(launch_op<double>(h->dim, g.P, OP_TRACE, A, g.nfmax, st));
+            A = make_args<double>(h, g, b, nullptr, h->d_tbuf2, nullptr);
+            HIPCHK(launch_op<double>(h->dim, g.P, OP_TRACE, A, g.nfmax, st));
+        }
         A = make_args<double>(h, g, nullptr, nullptr, nullptr, nullptr);
         A.tsz = work_size_for(h->dim, g.P, g.P + 2);
         HIPCHK(launch_pgrad_elem(h->dim, g.P, A, a, b, h->d_tau0, dlam, h->d_elem_tmp, st));
