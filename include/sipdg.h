@@ -38,7 +38,12 @@
  *     ordinary memory, read during the call only;
  *   - stream is a hipStream_t passed as void* (NULL = default stream);
  *     functions documented "async" only enqueue work on that stream;
- *   - a handle may be used by one stream at a time.
+ *   - a handle may be used by one stream at a time;
+ *   - a mesh with no elements is valid: on its handle every vector call
+ *     (apply, transpose, stages, diagonal, points, load vector, lambda,
+ *     parameter gradient, CG) does nothing and accepts null vectors; CG
+ *     reports convergence after 0 iterations and the penalty gradient of
+ *     each problem is 0.  A batch may hold such problems among others.
  */
 #ifndef SIPDG_H
 #define SIPDG_H

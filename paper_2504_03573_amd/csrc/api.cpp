@@ -663,7 +663,9 @@ int sipdg_problem_offsets(sipdg_handle h, int64_t *dof_off, int64_t *elem_off) {
 }
 
 int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *stream) {
-    if (!h || !x || !y) return fail(SIPDG_EINVAL, "null argument");
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->ndof == 0) return SIPDG_OK;   // empty mesh: nothing to do
+    if (!x || !y) return fail(SIPDG_EINVAL, "null argument");
     if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
     hipStream_t st = (hipStream_t)stream;
     if (precision == SIPDG_F64)
@@ -674,8 +676,10 @@ int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *str
 }
 
 int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int stage, void *stream) {
-    if (!h || !x || (stage == 2 && !y)) return fail(SIPDG_EINVAL, "null argument");
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (stage != 1 && stage != 2) return fail(SIPDG_EINVAL, "stage must be 1 or 2");
+    if (h->ndof == 0) return SIPDG_OK;
+    if (!x || (stage == 2 && !y)) return fail(SIPDG_EINVAL, "null argument");
     if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
     hipStream_t st = (hipStream_t)stream;
     if (precision == SIPDG_F64)
@@ -687,10 +691,15 @@ int sipdg_apply_stage(sipdg_handle h, const void *x, void *y, int precision, int
 
 int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int reps,
                       sipdg_launch_info *info, int max_launches, int *n_launches, void *stream) {
-    if (!h || !x || !y || !info || !n_launches) return fail(SIPDG_EINVAL, "null argument");
-    if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
+    if (!h || !info || !n_launches) return fail(SIPDG_EINVAL, "null argument");
     if (precision != SIPDG_F64 && precision != SIPDG_F32)
         return fail(SIPDG_EINVAL, "precision must be SIPDG_F64 or SIPDG_F32");
+    if (h->ndof == 0) {   // empty mesh: no launches
+        *n_launches = 0;
+        return SIPDG_OK;
+    }
+    if (!x || !y) return fail(SIPDG_EINVAL, "null argument");
+    if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
     if (reps <= 0) reps = 1;
     hipStream_t st = (hipStream_t)stream;
     const int per = 2 * (int)h->groups.size();     // launches of one application, at most
@@ -753,13 +762,17 @@ int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precisi
 }
 
 int sipdg_diagonal(sipdg_handle h, double *d, void *stream) {
-    if (!h || !d) return fail(SIPDG_EINVAL, "null argument");
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->ndof == 0) return SIPDG_OK;
+    if (!d) return fail(SIPDG_EINVAL, "null argument");
     HIPCHK(hipMemcpyAsync(d, h->d_diag64, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return SIPDG_OK;
 }
 
 int sipdg_set_lambda(sipdg_handle h, const double *lam, void *stream) {
-    if (!h || !lam) return fail(SIPDG_EINVAL, "null argument");
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->ne == 0) return SIPDG_OK;
+    if (!lam) return fail(SIPDG_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream;
     HIPCHK(hipMemcpyAsync(h->d_lam64, lam, sizeof(double) * h->ne, hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_cast_f32(h->d_lam64, h->d_lam32, h->ne, st));
@@ -792,14 +805,18 @@ int sipdg_num_points(sipdg_handle h, int64_t *nv, int64_t *nb) {
 }
 
 int sipdg_quad_points(sipdg_handle h, double *xq, double *xb, void *stream) {
-    if (!h || !xq || (!xb && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->ne == 0) return SIPDG_OK;
+    if (!xq || (!xb && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
     HIPCHK(launch_points(h->dim, h->ne, h->d_corners, h->d_order, h->d_eface, h->d_qoff, h->d_boff,
                          h->d_tab64, xq, xb, (hipStream_t)stream));
     return SIPDG_OK;
 }
 
 int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *b, void *stream) {
-    if (!h || !s || !b || (!g && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->ndof == 0) return SIPDG_OK;
+    if (!s || !b || (!g && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
     for (const Group &gr : h->groups) {
         OpArgs<double> A = make_args<double>(h, gr, nullptr, b, nullptr, nullptr);
         A.tsz = work_size_for(h->dim, gr.P, gr.P + 2);
@@ -810,8 +827,13 @@ int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *
 
 int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *dlam, double *dsig,
                      void *stream) {
-    if (!h || !a || !b || !dlam || !dsig) return fail(SIPDG_EINVAL, "null argument");
+    if (!h || !dsig) return fail(SIPDG_EINVAL, "null argument");
     hipStream_t st = (hipStream_t)stream;
+    if (h->ne == 0) {   // empty mesh: every problem's penalty gradient is zero
+        HIPCHK(hipMemsetAsync(dsig, 0, sizeof(double) * h->nprob, st));
+        return SIPDG_OK;
+    }
+    if (!a || !b || !dlam) return fail(SIPDG_EINVAL, "null argument");
     if (!h->d_tbuf2) {
         HIPCHK(hipMalloc((void **)&h->d_tbuf2, sizeof(double) * std::max<int64_t>(1, h->tbuf_len)));
         HIPCHK(hipMalloc((void **)&h->d_face_tmp, sizeof(double) * std::max<int64_t>(1, h->nfaces)));

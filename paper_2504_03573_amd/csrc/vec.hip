@@ -248,23 +248,27 @@ __global__ void k_fill(R *v, int64_t n, R val) {
 
 template <class R>
 hipError_t vec_dot(const VecCtx &V, const R *a, const R *b, double *partial, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_dot<R>, dim3(V.nblk), dim3(VB), 0, st, V, a, b, partial);
     LCHK();
 }
 template <class R>
 hipError_t vec_update(const VecCtx &V, const CgScalars &S, R *x, R *r, const R *p, const R *q,
                       const R *dinv, R *z, double *prr, double *prz, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_update<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, x, r, p, q, dinv, z, prr, prz);
     LCHK();
 }
 template <class R>
 hipError_t vec_pupdate(const VecCtx &V, const CgScalars &S, const R *z, R *p, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_pupdate<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, z, p);
     LCHK();
 }
 template <class R>
 hipError_t vec_start(const VecCtx &V, const R *r, const R *dinv, R *z, R *p, R *x, double *prr,
                      double *prz, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_start<R>, dim3(V.nblk), dim3(VB), 0, st, V, r, dinv, z, p, x, prr, prz);
     LCHK();
 }
@@ -295,14 +299,17 @@ hipError_t vec_fin_norm(const VecCtx &V, const double *part, double *out, hipStr
 }
 hipError_t vec_resid(const VecCtx &V, const double *b, const double *q, double *r, double *prr,
                      hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_resid, dim3(V.nblk), dim3(VB), 0, st, V, b, q, r, prr);
     LCHK();
 }
 hipError_t vec_scale32(const VecCtx &V, const double *r, const double *nrm, float *r32, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_scale32, dim3(V.nblk), dim3(VB), 0, st, V, r, nrm, r32);
     LCHK();
 }
 hipError_t vec_correct(const VecCtx &V, const float *d32, const double *nrm, double *x, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_correct, dim3(V.nblk), dim3(VB), 0, st, V, d32, nrm, x);
     LCHK();
 }

@@ -51,6 +51,7 @@ CASES = {
     "3d_p7_n2_rot": lambda: synth.small_mesh(3, 2, 7, seed=13, rotate=True, lam=2.0),
     "3d_checker78_n3": lambda: synth.small_mesh(3, 3, ("checker", 7, 8), seed=17, lam=1.0),
     "3d_single_elem_p2": lambda: synth.small_mesh(3, 1, 2, seed=1, lam=3.0),
+    "3d_lam0_p2to5_n2_rot": lambda: synth.small_mesh(3, 2, ("random", 2, 5), seed=21, rotate=True, lam=0.0),
     "w5_lamfield_n3": lambda: synth.workload(5, N=3),
 }
 
