@@ -39,8 +39,10 @@ struct Cfg {
     static constexpr int NFP = DIM == 3 ? N * N : N;      // element face points
     static constexpr int NQ = DIM + 1;                    // u and grad_xi u
     static constexpr int NGEO = DIM * (DIM + 1) / 2 + 1;  // G w (sym) + w|J|
-    static constexpr int EPB = DIM == 2 ? (BLOCK / (4 * N) > 0 ? BLOCK / (4 * N) : 1)
-                                        : (NPTS <= 160 ? 2 : 1);
+    // elements per block: 2-D, one (measured on the 64 x 64 mixed-order mesh:
+    // several per block left fewer blocks than compute units); 3-D, two up to
+    // order 3
+    static constexpr int EPB = DIM == 2 ? 1 : (NPTS <= 160 ? 2 : 1);
     static constexpr int TABSZ = N * NP + N * N;          // B and D in LDS
     static constexpr int TABPAD = (TABSZ + 3) & ~3;
 };
