@@ -175,16 +175,17 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
  *   FUSED:     as TWO_STAGE, but each element evaluates its neighbours'
  *              traces from their coefficients, so one launch per order group
  *              and no trace buffer.  3-D, orders <= 6.
- *   GATHER_FOLD: one wavefront per element with the volume in registers;
- *              the element's own face values are gathered from its GLL face
- *              points (interpolated with I when the trace is finer) and the
- *              lifted flux is added to the volume's pointwise terms so that
- *              one IProduct lifts faces and volume (Sec. 3.2 GathrInterp;
- *              Sec. 3.3).  A trace kernel stores every interior face side's
- *              (u, g), then the apply kernel reads the neighbour's.  3-D;
- *              an order group above 6, or touching a neighbour above 6, uses
- *              the GATHER kernels (same trace buffer).  Default in 3-D
- *              (GATHER in 2-D).
+ *   GATHER_FOLD: two stages.  The trace stage evaluates every face side's
+ *              (u, g) at the shared trace points from the element's
+ *              coefficients (TracePhysEval, Sec. 3.2), one launch for every
+ *              element of order <= 6 and one per order-7/8 group.  The apply
+ *              runs one wavefront per element (two for orders 7-8) with the
+ *              volume in registers; the flux from both sides' (u, g) is
+ *              lifted by the transposed interpolation and added to the
+ *              volume's pointwise terms so that one IProduct lifts faces and
+ *              volume (Sec. 3.3).  3-D; an order group <= 6 touching a
+ *              neighbour above 6 uses the GATHER kernels (same trace buffer).
+ *              Default in 3-D (GATHER in 2-D).
  *   GATHER_FOLD_PERSISTENT: as GATHER_FOLD, but each stage is one
  *              persistent launch for the elements of every order <= 6 of all
  *              problems (listed by decreasing order; a fixed number of blocks

@@ -138,5 +138,5 @@ struct sipdg_ctx {
     int num_cu = 256;
     int blocks_per_cu = 8;            // persistent grid = num_cu * blocks_per_cu
     bool fast_ok = false;   // 3-D with every order <= 6
-    bool gfold_ok = false;  // 3-D: gather-fold for order <= 6 groups, general kernels above
+    bool gfold_ok = false;  // 3-D: gather-fold (general kernels for groups <= 6 next to orders 7-8)
 };

@@ -647,10 +647,9 @@ __device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, cons
     lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
 }
 
-// (The trace stage is k3t_elem.)
 // MODE 1 (apply, two-stage): y = A x with both sides' (u, g) read from the
-//   trace buffer written by MODE 0 (the element's own face values and their
-//   interpolation are not needed again).
+//   trace buffer written by the trace stage (k3t_elem); orders 6 and 8 take
+//   their own (u, g) from their face values instead.
 // MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
 // One element: descriptor blk of A.desc / A.fdesc, LDS at smem_raw.
 template <class R, int P, int MODE>

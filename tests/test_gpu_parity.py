@@ -171,7 +171,7 @@ def test_variants_agree(case):
     ys = {}
     keep = op.variant
     if int(mesh.order.max()) > 6:
-        # gather-fold for orders <= 6 next to the general kernels above
+        # orders 7-8 present: only the structures that support them
         try:
             for v in ("gather", "gather_fold", "gather_fold_persistent"):
                 op.variant = v
