@@ -77,6 +77,7 @@ def test_workload4_batched_sampled(env):
     rng = np.random.default_rng(44)
     x = rng.standard_normal(bop.n_dofs)
     y = bop.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    y32 = bop.apply(torch.tensor(x, device="cuda", dtype=torch.float32)).double().cpu().numpy()
     off = bop.problem_dof_offsets
     for i in rng.choice(len(meshes), size=3, replace=False):
         m = meshes[i]
@@ -87,3 +88,23 @@ def test_workload4_batched_sampled(env):
         rows = _rows(om, om.dof_off, elems)
         yi = y[off[i]:off[i + 1]]
         assert np.linalg.norm(yi[rows] - y_ref[rows]) <= 1e-12 * np.linalg.norm(y_ref[rows]), i
+        yi32 = y32[off[i]:off[i + 1]]
+        assert np.linalg.norm(yi32[rows] - y_ref[rows]) <= 1e-5 * np.linalg.norm(y_ref[rows]), i
+
+
+def test_workload3_cg_full(env):
+    """The solves the benchmark times, at full size: both modes reach a true
+    relative residual of 1e-10 (recomputed here with an FP64 apply)."""
+    P, oracle = env
+    print("[workload 3 cg]", flush=True)
+    import math
+    m = synth.workload(3)
+    op = P.SipdgOperator(m)
+    k = math.pi
+    b = op.rhs(lambda X: (10 + 3 * k * k) * torch.sin(k * X[:, 0]) * torch.sin(k * X[:, 1]) * torch.sin(k * X[:, 2]),
+               lambda X: torch.zeros(X.shape[0], dtype=torch.float64, device=X.device))
+    for mode in ("f64", "f32_ir"):
+        xs, info = op.cg_solve(b, tol=1e-10, mode=mode)
+        r = float((b - op.apply(xs)).norm() / b.norm())
+        print(f"workload 3 {mode}: {info}, recomputed residual {r:.3e}", flush=True)
+        assert info["converged"] and r <= 1e-10 * (1 + 1e-6), (mode, r)
