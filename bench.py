@@ -310,7 +310,9 @@ def main():
 
         bvec = op.rhs(src, lambda X: torch.zeros(X.shape[0], dtype=torch.float64, device=X.device))
         cg = {}
-        for mode in ("f64", "f32_ir"):
+        # f64: FP64 PCG; f32_ir: FP32 PCG inside FP64 iterative refinement;
+        # f32_ru: FP32 PCG with FP64 reliable updates (residual replaced every 10x)
+        for mode in ("f64", "f32_ir", "f32_ru"):
             op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=50, raise_on_fail=False)  # graph capture
             torch.cuda.synchronize()
             xs, info = op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=100000, raise_on_fail=False)

@@ -245,17 +245,21 @@ int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *
 
 #define SIPDG_CG_F64     0   /* FP64 Jacobi-PCG */
 #define SIPDG_CG_F32_IR  1   /* FP32 inner PCG inside FP64 iterative refinement */
+#define SIPDG_CG_F32_RU  2   /* FP32 PCG with FP64 reliable updates: as F32_IR, but at each
+                                FP64 residual replacement the FP32 recursion continues with its
+                                search direction (renormalised) instead of restarting */
 
 typedef struct {
     double tol;        /* stop when ||b - A x||_2 <= tol ||b||_2 per problem (1e-10) */
     int maxit;         /* max total (inner) iterations, per solve */
-    int mode;          /* SIPDG_CG_F64 or SIPDG_CG_F32_IR */
-    double inner_tol;  /* F32_IR: smallest relative reduction one inner FP32 solve is
+    int mode;          /* SIPDG_CG_F64, SIPDG_CG_F32_IR or SIPDG_CG_F32_RU */
+    double inner_tol;  /* F32_IR, F32_RU: smallest relative reduction one inner FP32 cycle is
                           asked for (1e-4); each inner solve asks for what the outer
                           residual still needs, max(inner_tol, tol ||b|| / (2 ||r||)) */
     int precond;       /* 1 = Jacobi, 0 = none */
     int graph_k;       /* iterations per captured HIP graph / per host check; 0 = no graph */
-    int max_outer;     /* F32_IR: max refinement steps; F64: max restarts from the true residual, plus one (50) */
+    int max_outer;     /* F32_IR / F32_RU: max refinement steps / residual replacements;
+                          F64: max restarts from the true residual, plus one (50) */
     /* optional checkpoint: called every checkpoint_every iterations with the
      * device pointers of the FP64 iterate x and residual r and the iteration
      * count; x0_given = 1 starts from the x passed in (resume). */
@@ -263,6 +267,9 @@ typedef struct {
     void *checkpoint_user;
     int checkpoint_every;
     int x0_given;
+    double ru_delta;   /* F32_RU: replace the residual once the FP32 residual has dropped by
+                          this factor (0.1); a problem whose true residual then exceeds 1.5x
+                          its recursive estimate restarts instead of continuing */
 } sipdg_cg_opts;
 
 typedef struct {

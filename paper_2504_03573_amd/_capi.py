@@ -24,6 +24,7 @@ SIPDG_F64 = 0
 SIPDG_F32 = 1
 SIPDG_CG_F64 = 0
 SIPDG_CG_F32_IR = 1
+SIPDG_CG_F32_RU = 2
 MAX_ORDER = 8
 VARIANTS = {"gather": 0, "two_stage": 1, "fused": 2, "gather_fold": 3, "gather_fold_fused": 4,
             "gather_fold_persistent": 5}
@@ -77,6 +78,7 @@ class CgOpts(ctypes.Structure):
         ("checkpoint_user", ctypes.c_void_p),
         ("checkpoint_every", ctypes.c_int),
         ("x0_given", ctypes.c_int),
+        ("ru_delta", ctypes.c_double),
     ]
 
 

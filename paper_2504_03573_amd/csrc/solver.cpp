@@ -36,6 +36,7 @@ struct CgWork {
     double *x64 = nullptr, *r64 = nullptr, *z64 = nullptr, *pp64 = nullptr, *q64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *pp32 = nullptr, *q32 = nullptr;
     double *d_norm = nullptr, *d_bnorm = nullptr;
+    double *d_ratio = nullptr;   // [nprob] residual-norm ratio of a reliable update
     int *d_preconv = nullptr;
     hipGraphExec_t g64 = nullptr, g32 = nullptr;
     int gk64 = 0, gk32 = 0;
@@ -49,7 +50,7 @@ void free_cg(sipdg_ctx *c) {
     if (w->g32) (void)hipGraphExecDestroy(w->g32);
     void *ptrs[] = {w->d_blk_start, w->d_blk_prob, w->d_prob_blk, w->d_done, w->d_sc, w->d_si,
                     w->p1, w->p2, w->x64, w->r64, w->z64, w->pp64, w->q64, w->x32, w->r32,
-                    w->z32, w->pp32, w->q32, w->d_norm, w->d_bnorm, w->d_preconv};
+                    w->z32, w->pp32, w->q32, w->d_norm, w->d_bnorm, w->d_preconv, w->d_ratio};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w->stream) (void)hipStreamDestroy(w->stream);
@@ -122,6 +123,7 @@ static int ensure_cg(sipdg_ctx *c) {
     ALLOC(w->d_norm, np);
     ALLOC(w->d_bnorm, np);
     ALLOC(w->d_preconv, np);
+    ALLOC(w->d_ratio, np);
     return SIPDG_OK;
 }
 
@@ -260,6 +262,7 @@ void sipdg_cg_default_opts(sipdg_cg_opts *o) {
     o->precond = 1;
     o->graph_k = 10;
     o->max_outer = 50;
+    o->ru_delta = 0.1;
 }
 
 int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_opts *opts,
@@ -268,9 +271,12 @@ int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_op
     sipdg_cg_opts o;
     if (opts) o = *opts;
     else sipdg_cg_default_opts(&o);
-    if (!(o.tol > 0.0) || o.maxit <= 0 || (o.mode != SIPDG_CG_F64 && o.mode != SIPDG_CG_F32_IR))
+    if (!(o.tol > 0.0) || o.maxit <= 0 ||
+        (o.mode != SIPDG_CG_F64 && o.mode != SIPDG_CG_F32_IR && o.mode != SIPDG_CG_F32_RU))
         return fail(SIPDG_EINVAL, "invalid CG options");
-    if (o.mode == SIPDG_CG_F32_IR && !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
+    if (o.mode == SIPDG_CG_F32_RU && !(o.ru_delta > 0.0 && o.ru_delta < 1.0))
+        return fail(SIPDG_EINVAL, "ru_delta must be in (0, 1)");
+    if (o.mode != SIPDG_CG_F64 && !(o.inner_tol > 0.0 && o.inner_tol < 1.0))
         return fail(SIPDG_EINVAL, "inner_tol must be in (0, 1)");
     if (h->ndof == 0) {   // empty mesh: the (empty) zero vector solves it
         if (info) {
@@ -353,6 +359,7 @@ int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_op
         rc = ensure_cg32(h);
         if (rc) return rc;
         std::vector<int> preconv(h->nprob);
+        std::vector<double> nr_prev(h->nprob, 0.0);   // residual norms of the previous cycle
         while (true) {
             rc = apply_impl<double>(h, w->x64, w->q64, h->d_tbuf, nullptr, st);
             if (rc) return rc;
@@ -375,12 +382,34 @@ int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_op
             double itol = 1.0;
             for (int p = 0; p < h->nprob; ++p)
                 if (!preconv[p] && nr[p] > 0.0) itol = std::min(itol, 0.5 * o.tol * bn[p] / nr[p]);
-            itol = std::min(std::max(itol, o.inner_tol), 0.5);
+            itol = std::min(std::max(itol, o.mode == SIPDG_CG_F32_RU ? o.ru_delta : o.inner_tol), 0.5);
             HIPCHK(hipMemcpyAsync(w->d_preconv, preconv.data(), sizeof(int) * h->nprob, hipMemcpyHostToDevice, st));
             HIPCHK(vec_scale32(w->V, w->r64, w->d_norm, w->r32, st));
-            HIPCHK(vec_start<float>(w->V, w->r32, o.precond ? h->d_dinv32 : nullptr, w->z32, w->pp32,
-                                    w->x32, w->p1, w->p2, st));
-            HIPCHK(vec_fin_start(w->V, w->S, w->p1, w->p2, nullptr, w->d_preconv, itol, st));
+            if (o.mode == SIPDG_CG_F32_IR || outer == 0) {
+                // refinement: a fresh FP32 PCG on the normalised residual
+                HIPCHK(vec_start<float>(w->V, w->r32, o.precond ? h->d_dinv32 : nullptr, w->z32, w->pp32,
+                                        w->x32, w->p1, w->p2, st));
+                HIPCHK(vec_fin_start(w->V, w->S, w->p1, w->p2, nullptr, w->d_preconv, itol, st));
+            } else {
+                // reliable update: the true residual replaces the recursive one,
+                // the search direction is kept (renormalised) and the recursion goes on
+                // continue a problem only if its true residual agrees with the
+                // FP32 recursion's estimate (rel: reduction reached in the cycle);
+                // else restart it (ratio 0 gives p = z)
+                std::vector<double> rel_rec(h->nprob), ratio(h->nprob, 0.0);
+                HIPCHK(hipMemcpyAsync(rel_rec.data(), w->S.rel, sizeof(double) * h->nprob, hipMemcpyDeviceToHost,
+                                      st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (int p = 0; p < h->nprob; ++p)
+                    if (nr_prev[p] > 0.0 && nr[p] <= 1.5 * rel_rec[p] * nr_prev[p]) ratio[p] = nr[p] / nr_prev[p];
+                HIPCHK(hipMemcpyAsync(w->d_ratio, ratio.data(), sizeof(double) * h->nprob, hipMemcpyHostToDevice,
+                                      st));
+                HIPCHK(vec_start<float>(w->V, w->r32, o.precond ? h->d_dinv32 : nullptr, w->z32, nullptr, w->x32,
+                                        w->p1, w->p2, st));
+                HIPCHK(vec_fin_cont(w->V, w->S, w->p1, w->p2, w->d_preconv, w->d_ratio, itol, st));
+                HIPCHK(vec_pupdate<float>(w->V, w->S, w->z32, w->pp32, st));
+            }
+            nr_prev = nr;
             int it = 0, idone = 0;
             rc = cg_loop<float>(h, o, itol, o.maxit - total_iters, it, flags, idone, false, total_iters);
             if (rc) return rc;

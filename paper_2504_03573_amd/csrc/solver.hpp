@@ -48,6 +48,8 @@ hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, 
                         hipStream_t st);
 hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
                          const double *bnorm_src, const int *preconv, double tol, hipStream_t st);
+hipError_t vec_fin_cont(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
+                        const int *preconv, const double *ratio, double tol, hipStream_t st);
 hipError_t vec_fin_norm(const VecCtx &V, const double *part, double *out, hipStream_t st);
 hipError_t vec_resid(const VecCtx &V, const double *b, const double *q, double *r, double *prr,
                      hipStream_t st);

@@ -61,11 +61,12 @@ __global__ __launch_bounds__(VB) void k_update(VecCtx V, const CgScalars S, R *x
     }
 }
 
-// p = z + beta p
+// p = z + beta p; a stopped problem keeps its last direction
 template <class R>
 __global__ __launch_bounds__(VB) void k_pupdate(VecCtx V, const CgScalars S, const R *z, R *p) {
     if (V.done && *V.done) return;
     const int prob = V.blk_prob[blockIdx.x];
+    if (S.conv[prob]) return;
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
     const double beta = S.beta[prob];
     for (int64_t i = s + threadIdx.x; i < e; i += VB) p[i] = (R)((double)z[i] + beta * (double)p[i]);
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(VB) void k_start(VecCtx V, const R *r, const R *din
         const R ri = r[i];
         const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
         z[i] = zi;
-        p[i] = zi;
+        if (p) p[i] = zi;   // null: keep the search direction (reliable update)
         if (x) x[i] = (R)0;
         rr += (double)ri * (double)ri;
         rz += (double)ri * (double)zi;
@@ -189,6 +190,37 @@ __global__ __launch_bounds__(VB) void k_fin_start(VecCtx V, CgScalars S, const d
     S.iters[p] = 0;
     S.rel[p] = bn > 0.0 ? sqrt(rr) / bn : 0.0;
     const bool c = (preconv && preconv[p]) || !(bn > 0.0) || sqrt(rr) <= tol * bn;
+    S.conv[p] = c ? 1 : 0;
+    int total = 0;
+    if (last_vote(S.nact, S.nfin, !c, total)) {
+        *V.done = total == 0 ? 1 : 0;
+        S.counter[0] = 0;
+        S.flags[0] = 0;
+        S.tol[0] = tol;
+    }
+}
+
+// Continuation after a reliable update (one block per problem): r was
+// replaced by the true residual, renormalised by ratio = ||r_new|| / ||r_old||
+// of the unnormalised residuals, and z = M r recomputed; the search direction
+// p is kept.  rho' = r.z; beta = (rho' / rho) ratio makes p = z + beta p the
+// next conjugate direction in the new normalisation (rho from the last step
+// that used p); conv as in k_fin_start.
+__global__ __launch_bounds__(VB) void k_fin_cont(VecCtx V, CgScalars S, const double *prr, const double *prz,
+                                                  const int *preconv, const double *ratio, double tol) {
+    __shared__ double red[VB];
+    const int p = blockIdx.x;
+    const double rr = seg_sum(prr, V.prob_blk[p], V.prob_blk[p + 1], red);
+    const double rz = seg_sum(prz, V.prob_blk[p], V.prob_blk[p + 1], red);
+    if (threadIdx.x != 0) return;
+    const double bn = sqrt(rr);
+    const double rho = S.rho[p];
+    const bool c = (preconv && preconv[p]) || !(bn > 0.0) || sqrt(rr) <= tol * bn;
+    S.bnorm[p] = bn;
+    S.beta[p] = (!c && rho > 0.0) ? (rz / rho) * ratio[p] : 0.0;
+    S.rho[p] = rz;
+    S.alpha[p] = 0.0;
+    S.rel[p] = bn > 0.0 ? 1.0 : 0.0;
     S.conv[p] = c ? 1 : 0;
     int total = 0;
     if (last_vote(S.nact, S.nfin, !c, total)) {
@@ -291,6 +323,11 @@ hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, 
 hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
                          const double *bnorm_src, const int *preconv, double tol, hipStream_t st) {
     hipLaunchKernelGGL(k_fin_start, dim3(V.nprob), dim3(VB), 0, st, V, S, prr, prz, bnorm_src, preconv, tol);
+    LCHK();
+}
+hipError_t vec_fin_cont(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
+                        const int *preconv, const double *ratio, double tol, hipStream_t st) {
+    hipLaunchKernelGGL(k_fin_cont, dim3(V.nprob), dim3(VB), 0, st, V, S, prr, prz, preconv, ratio, tol);
     LCHK();
 }
 hipError_t vec_fin_norm(const VecCtx &V, const double *part, double *out, hipStream_t st) {

@@ -231,7 +231,7 @@ class SipdgOperator:
         return self.load_vector(s, g)
 
     def cg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
-                 maxit: int = 20000, mode: str = "f64", inner_tol: float = 1e-4,
+                 maxit: int = 20000, mode: str = "f64", inner_tol: float = 1e-4, ru_delta: float = 0.1,
                  precond: bool = True, graph_k: int = 10, max_outer: int = 50,
                  checkpoint=None, checkpoint_every: int = 0, x0: torch.Tensor | None = None,
                  stream=None, raise_on_fail: bool = True):
@@ -243,8 +243,8 @@ class SipdgOperator:
         self._vec(x, torch.float64, name="x")
         o = C.CgOpts()
         self._lib.sipdg_cg_default_opts(ctypes.byref(o))
-        o.tol, o.maxit, o.inner_tol = float(tol), int(maxit), float(inner_tol)
-        o.mode = {"f64": C.SIPDG_CG_F64, "f32_ir": C.SIPDG_CG_F32_IR}[mode]
+        o.tol, o.maxit, o.inner_tol, o.ru_delta = float(tol), int(maxit), float(inner_tol), float(ru_delta)
+        o.mode = {"f64": C.SIPDG_CG_F64, "f32_ir": C.SIPDG_CG_F32_IR, "f32_ru": C.SIPDG_CG_F32_RU}[mode]
         o.precond, o.graph_k, o.max_outer = int(precond), int(graph_k), int(max_outer)
         cb_keep = None
         if checkpoint is not None and checkpoint_every > 0:

@@ -191,7 +191,7 @@ def test_batch_cg_per_problem(P):
     xt = torch.tensor(rng.standard_normal(bop.n_dofs), device="cuda")
     b = bop.apply(xt)
     off = bop.problem_dof_offsets
-    for mode in ("f64", "f32_ir"):
+    for mode in ("f64", "f32_ir", "f32_ru"):
         xs, info = bop.cg_solve(b, tol=1e-10, mode=mode)
         assert info["converged"] and info["rel_resid"] <= 1e-10, info
         r = b - bop.apply(xs)

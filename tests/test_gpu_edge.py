@@ -39,7 +39,7 @@ def test_empty_mesh(P):
         assert op.apply(x).numel() == 0
     x = torch.empty(0, dtype=torch.float64, device="cuda")
     assert op.apply_transpose(x).numel() == 0
-    for mode in ("f64", "f32_ir"):
+    for mode in ("f64", "f32_ir", "f32_ru"):
         xs, info = op.cg_solve(x, tol=1e-10, mode=mode)
         assert xs.numel() == 0 and info["converged"] and info["iters"] == 0 and info["rel_resid"] == 0.0
     dl, ds = op.param_grad(x, x)
@@ -61,7 +61,7 @@ def test_batch_with_empty_problem(P):
     y = bop.apply(x)
     for op, i in zip(singles, (0, 2)):
         assert torch.equal(op.apply(x[off[i]:off[i + 1]].contiguous()), y[off[i]:off[i + 1]]), i
-    for mode in ("f64", "f32_ir"):
+    for mode in ("f64", "f32_ir", "f32_ru"):
         xs, info = bop.cg_solve(y, tol=1e-10, mode=mode)
         assert info["converged"] and info["rel_resid"] <= 1e-10, (mode, info)
         r = y - bop.apply(xs)

@@ -149,9 +149,10 @@ def test_cg_f32_ir(case):
     name, mesh, op, om = case
     x_true = synth.random_coefficients(mesh, 4004)
     b = op.apply(torch.tensor(x_true, device="cuda"))
-    xs, info = op.cg_solve(b, tol=1e-10, mode="f32_ir")
-    print(f"{name}: f32_ir {info}")
-    assert info["converged"] and info["rel_resid"] <= 1e-10
+    for mode in ("f32_ir", "f32_ru"):
+        xs, info = op.cg_solve(b, tol=1e-10, mode=mode)
+        print(f"{name}: {mode} {info}")
+        assert info["converged"] and info["rel_resid"] <= 1e-10, mode
     xg, info_g = op.cg_solve(b, tol=1e-10, graph_k=0)
     xh, info_h = op.cg_solve(b, tol=1e-10, graph_k=7)
     assert torch.equal(xg, xh) or info_g["iters"] == info_h["iters"]
