@@ -108,3 +108,15 @@ def test_create_without_device_reports_error(capi):
     with pytest.raises(capi.SipdgError) as ei:
         SipdgOperator(synth.small_mesh(2, 2, 3, seed=1))
     assert ei.value.code == -4
+
+
+def test_cg_default_opts_layout(capi):
+    """The ctypes mirror of sipdg_cg_opts matches the C struct: the library's
+    defaults land in the right fields (no device needed)."""
+    lib = capi.load()
+    o = capi.CgOpts()
+    lib.sipdg_cg_default_opts(ctypes.byref(o))
+    assert o.tol == 1e-10 and o.maxit == 20000 and o.mode == capi.SIPDG_CG_F64
+    assert o.inner_tol == 1e-4 and o.precond == 1 and o.graph_k == 10 and o.max_outer == 50
+    assert o.checkpoint_every == 0 and o.x0_given == 0 and o.ru_delta == 0.1
+    assert capi.SIPDG_CG_F32_RU == 2
