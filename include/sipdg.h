@@ -232,6 +232,16 @@ int sipdg_set_penalty_scale(sipdg_handle h, int problem, double sigma);
 
 /* Number of volume quadrature points and of boundary trace points. */
 int sipdg_num_points(sipdg_handle h, int64_t *n_volume, int64_t *n_boundary);
+
+/* Number of elements found affine at create (3-D: the 8 corners span a
+ * parallelepiped to within 1e-14 of the longest edge plus 16 ulp of the
+ * largest corner coordinate, so the Jacobian is constant to rounding).
+ * These are the regular elements of Sec. 5.1: the default gather-fold apply
+ * reads their 6 entries of |J| J^-1 J^-T and |J| once per element instead of
+ * 7 values per quadrature point, in a launch of their own.
+ * Detection is off when the environment variable SIPDG_NO_AFFINE is "1" at
+ * create.  2-D handles: 0.  Errors: EINVAL (null handle or pointer). */
+int sipdg_num_affine(sipdg_handle h, int64_t *n_affine);
 /* Physical coordinates (device FP64, [n][dim]) of the volume quadrature
  * points (element by element, points lexicographic) and of the boundary
  * trace points (element by element, boundary faces in local face order

@@ -123,6 +123,7 @@ SIGNATURES = {
     "sipdg_set_lambda": (_i, [_vp, _vp, _vp]),
     "sipdg_set_penalty_scale": (_i, [_vp, _i, _d]),
     "sipdg_num_points": (_i, [_vp, c_int64_p, c_int64_p]),
+    "sipdg_num_affine": (_i, [_vp, c_int64_p]),
     "sipdg_quad_points": (_i, [_vp, _vp, _vp, _vp]),
     "sipdg_load_vector": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "sipdg_cg_default_opts": (None, [ctypes.POINTER(CgOpts)]),

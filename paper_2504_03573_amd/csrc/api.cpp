@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -139,6 +140,13 @@ static bool gfold_group(const Group &g, bool fused) {
     return !fused && g.P >= 7 && g.P <= 8 && g.nfmax <= 10;
 }
 
+// per-element constants of affine elements (G~, |J|), in the apply's precision
+template <class R>
+static const R *egeo_of(const sipdg_ctx *c) {
+    if constexpr (sizeof(R) == 8) return (const R *)c->d_egeo64;
+    else return (const R *)c->d_egeo32;
+}
+
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
                LaunchRec *rec) {
@@ -152,7 +160,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, c->d_pdesc, c->d_pfdesc};
-                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
                 rec_mark(rec, stage, -1, false, st);
                 hipError_t e = launch_gfold3d_persistent<R>(stage == 1 ? 0 : 1, c->num_cu * c->blocks_per_cu, A, D, st);
                 rec_mark(rec, stage, -1, true, st);
@@ -171,7 +179,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                     fast_args<R>(c, g, x, y, tbuf, skip, false, A3, D3);
                     g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
                                A3.toff, A3.skip, g.d_desc, g.d_fdesc};
-                    g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                    g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
                     e = launch_gfold3d<R>(g.P, stage == 1 ? 0 : 1, g.nfmax, A, D, st);
                 } else {
                     OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
@@ -204,7 +212,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, c->d_pdesc, c->d_pfdesc};
-                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
                 rec_mark(rec, stage, -1, false, main_st);
                 hipError_t e = launch_gfold3d_trace_all<R>(A, D, main_st);
                 rec_mark(rec, stage, -1, true, main_st);
@@ -243,9 +251,39 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
                 g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, g.d_desc, g.d_fdesc};
-                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
                 rec_mark(rec, stage, (int)gi, false, st);
-                hipError_t e = launch_gfold3d<R>(g.P, mode, g.nfmax, A, D, st);
+                hipError_t e = hipSuccess;
+                if (mode == 1 && g.split) {
+                    // the group's affine elements (first in its descriptors) and
+                    // the deformed rest.  Under graph capture side by side (the
+                    // fork and join are graph edges); eagerly one after the
+                    // other, since an event fork and join per group costs more
+                    // than the overlap of the two launches' tails gains
+                    g3::Args Aa = A, Ad = A;
+                    Aa.count = g.naff;
+                    Ad.count = g.count - g.naff;
+                    Ad.desc = g.d_desc + g.naff;
+                    Ad.fdesc = g.d_fdesc + (int64_t)6 * g.naff;
+                    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+                    if (Ad.count > 0 && c->aff_stream && !rec && hipStreamIsCapturing(st, &cap) != hipSuccess)
+                        return fail(SIPDG_EHIP, "stream capture query");
+                    const bool side = cap == hipStreamCaptureStatusActive;
+                    if (side) {
+                        if (hipEventRecord(c->aff_ev[0], st) != hipSuccess ||
+                            hipStreamWaitEvent(c->aff_stream, c->aff_ev[0], 0) != hipSuccess)
+                            return fail(SIPDG_EHIP, "event record / wait (affine fork)");
+                    }
+                    e = launch_gfold3d<R>(g.P, 3, g.nfmax, Aa, D, side ? c->aff_stream : st);
+                    if (e == hipSuccess) e = launch_gfold3d<R>(g.P, 1, g.nfmax, Ad, D, st);
+                    if (side) {
+                        if (hipEventRecord(c->aff_ev[1], c->aff_stream) != hipSuccess ||
+                            hipStreamWaitEvent(st, c->aff_ev[1], 0) != hipSuccess)
+                            return fail(SIPDG_EHIP, "event record / wait (affine join)");
+                    }
+                } else {
+                    e = launch_gfold3d<R>(g.P, mode, g.nfmax, A, D, st);
+                }
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
                     return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
@@ -342,11 +380,14 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_corners, c->d_tab64, c->d_tab32, c->d_vgeo64, c->d_fgeo64, c->d_lam64,
                     c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
-                    c->d_dinv64, c->d_dinv32};
+                    c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->d_pdesc) (void)hipFree(c->d_pdesc);
     if (c->d_pfdesc) (void)hipFree(c->d_pfdesc);
+    if (c->aff_stream) (void)hipStreamDestroy(c->aff_stream);
+    for (hipEvent_t ev : c->aff_ev)
+        if (ev) (void)hipEventDestroy(ev);
     for (hipStream_t sg : c->gstreams)
         if (sg) (void)hipStreamDestroy(sg);
     for (hipEvent_t ev : c->gevents)
@@ -424,6 +465,68 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
     TRY(upload(&c->d_faces, T.faces));
     TRY(upload(&c->d_order, T.order));
     TRY(upload(&c->d_corners, T.corners));
+    // affine (parallelepiped) elements: G~ and |J| are constant over the element
+    // (the paper's regular-element specialisation); the gather-fold apply then
+    // reads 7 values per element instead of 7 per point
+    std::vector<int> affine(T.ne, 0);
+    {
+        std::vector<double> eg((size_t)std::max<int64_t>(T.ne, 1) * 8, 0.0);
+        const char *off = std::getenv("SIPDG_NO_AFFINE");
+        if (T.dim == 3 && !(off && off[0] == '1')) {
+            for (int64_t e = 0; e < T.ne; ++e) {
+                const double *X = &T.corners[(size_t)e * 24];
+                double E[3][3], diam = 0.0, xmax = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    double n2 = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        E[k][a] = X[(1 << k) * 3 + a] - X[a];
+                        n2 += E[k][a] * E[k][a];
+                    }
+                    diam = std::max(diam, std::sqrt(n2));
+                }
+                for (int i = 0; i < 24; ++i) xmax = std::max(xmax, std::fabs(X[i]));
+                // a parallelepiped up to the rounding of the corner coordinates:
+                // the constant Jacobian then differs from the per-point one by
+                // about tol / edge, far below the FP64 parity bar
+                const double tol = 1e-14 * diam + 16.0 * DBL_EPSILON * xmax;
+                bool ok = diam > 0.0;
+                for (int v = 0; v < 8 && ok; ++v)
+                    for (int a = 0; a < 3; ++a) {
+                        double pred = X[a];
+                        for (int k = 0; k < 3; ++k)
+                            if ((v >> k) & 1) pred += E[k][a];
+                        if (std::fabs(X[v * 3 + a] - pred) > tol) ok = false;
+                    }
+                if (!ok) continue;
+                double J[3][3], A[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int k = 0; k < 3; ++k) J[a][k] = 0.5 * E[k][a];
+                A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+                A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+                A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+                A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+                A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+                A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+                A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+                A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+                A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+                if (!(det > 0.0)) continue;
+                int cidx = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = a; b < 3; ++b) {
+                        double t = 0.0;
+                        for (int cc = 0; cc < 3; ++cc) t += A[a][cc] * A[b][cc];
+                        eg[(size_t)e * 8 + cidx++] = t / det;
+                    }
+                eg[(size_t)e * 8 + 6] = det;
+                affine[e] = 1;
+            }
+        }
+        TRY(upload(&c->d_egeo64, eg));
+        TRY(dalloc(&c->d_egeo32, (int64_t)eg.size()));
+        TRYHIP(launch_cast_f32(c->d_egeo64, c->d_egeo32, (int64_t)eg.size(), 0));
+    }
     TRY(upload(&c->d_tau0, T.tau0));
     {
         std::vector<int> interior(T.nfaces), nf(T.nfaces);
@@ -489,7 +592,9 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
                 const double wb = w == 0 ? 8.0 : 4.0;
                 double sum = 0;
                 for (int e : ids) {
-                    sum += wb * (2.0 * nm + npts * (d * (d + 1) / 2 + 1) + 1);
+                    // geometry: per-point factors, or 7 constants of an affine element
+                    const double ng = affine[e] ? 7.0 : (double)npts * (d * (d + 1) / 2 + 1);
+                    sum += wb * (2.0 * nm + ng + 1);
                     for (int f = 0; f < nlf; ++f) {
                         const FaceRef fr = T.eface[(size_t)e * nlf + f];
                         const int nf = face_nf(fr.info);
@@ -503,11 +608,23 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         }
         c->groups.push_back(g);
         if (T.dim == 3) {
+            // groups at least half affine: affine elements first in the
+            // descriptors (an apply launch of their own).  Below half, two
+            // half-filled launches cost more than the affine part saves
+            // (measured on 32^3 meshes, orders 3-6): the group keeps element
+            // order and reads per-point factors.
+            int naff = 0;
+            for (int e : ids) naff += affine[e];
+            const bool split = naff > 0 && 2 * naff >= (int)ids.size();
+            std::vector<int> ord(ids);
+            if (split) std::stable_partition(ord.begin(), ord.end(), [&](int e) { return affine[e] != 0; });
+            c->groups.back().naff = naff;
+            c->groups.back().split = split;
             std::vector<ElemDesc> desc(ids.size());
             std::vector<FaceDesc> fdesc(ids.size() * 6);
-            for (size_t i = 0; i < ids.size(); ++i) {
-                const int64_t e = ids[i];
-                desc[i] = ElemDesc{T.xoff[e], T.voff[e], (int)e, 0};
+            for (size_t i = 0; i < ord.size(); ++i) {
+                const int64_t e = ord[i];
+                desc[i] = ElemDesc{T.xoff[e], T.voff[e], (int)e, affine[e] ? ELEM_AFFINE : 0};
                 for (int f = 0; f < 6; ++f) {
                     const FaceRef fr = T.eface[(size_t)e * 6 + f];
                     fdesc[i * 6 + f] = FaceDesc{T.foff[fr.F], T.toff[fr.F], fr.F, fr.info};
@@ -543,7 +660,7 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
                     TRYHIP(hipMemcpy(pd.data() + base, g.d_desc, sizeof(ElemDesc) * g.count, hipMemcpyDeviceToHost));
                     TRYHIP(hipMemcpy(pf.data() + base * 6, g.d_fdesc, sizeof(FaceDesc) * 6 * g.count,
                                      hipMemcpyDeviceToHost));
-                    for (int i = 0; i < g.count; ++i) pd[base + i].pad = P;
+                    for (int i = 0; i < g.count; ++i) pd[base + i].pad |= P;   // keeps ELEM_AFFINE
                 }
             }
             c->pcount = (int)pd.size();
@@ -554,6 +671,12 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
             hipDeviceProp_t prop;
             TRYHIP(hipGetDeviceProperties(&prop, c->device));
             c->num_cu = prop.multiProcessorCount;
+        }
+        bool part_affine = false;
+        for (const Group &g : c->groups) part_affine |= g.split && g.naff < g.count;
+        if (part_affine) {
+            TRYHIP(hipStreamCreateWithFlags(&c->aff_stream, hipStreamNonBlocking));
+            for (auto &ev : c->aff_ev) TRYHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         }
         if (c->groups.size() > 1) {
             c->gstreams.assign(c->groups.size(), nullptr);
@@ -801,6 +924,15 @@ int sipdg_num_points(sipdg_handle h, int64_t *nv, int64_t *nb) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (nv) *nv = h->nvq;
     if (nb) *nb = h->nbq;
+    return SIPDG_OK;
+}
+
+int sipdg_num_affine(sipdg_handle h, int64_t *n_affine) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (!n_affine) return fail(SIPDG_EINVAL, "null argument");
+    int64_t n = 0;
+    for (const Group &g : h->groups) n += g.naff;
+    *n_affine = n;
     return SIPDG_OK;
 }
 

@@ -61,8 +61,10 @@ struct OpArgs {
 // of its six faces in one round of loads.
 struct ElemDesc {
     int64_t xoff, voff;     // coefficient and volume-factor offsets
-    int e, pad;             // element id
+    int e, pad;             // element id; pad: order (persistent lists) | AFFINE
 };
+constexpr int ELEM_AFFINE = 0x100;   // the element's map is affine: constant G~ and |J|
+constexpr int ELEM_ORDER_MASK = 0xff;
 struct FaceDesc {
     int64_t fo, to;         // face-factor and trace-buffer offsets
     int F, info;            // face id and FaceRef::info
@@ -73,7 +75,9 @@ struct Group {
     int count;
     int nfmax;              // largest trace that touches the group
     int *d_elems;
-    ElemDesc *d_desc = nullptr;      // [count]      (3-D)
+    ElemDesc *d_desc = nullptr;      // [count]      (3-D); split: the naff affine elements first
+    int naff = 0;                    // affine elements of the group (3-D)
+    bool split = false;              // apply: affine part and deformed part launched apart
     FaceDesc *d_fdesc = nullptr;     // [count][6]   (3-D)
     double alg_bytes[2] = {0, 0};    // algorithmic bytes of the group's elements (FP64, FP32)
 };
@@ -116,6 +120,10 @@ struct sipdg_ctx {
     float *d_tab32 = nullptr;
     double *d_vgeo64 = nullptr, *d_fgeo64 = nullptr, *d_lam64 = nullptr, *d_tau64 = nullptr;
     float *d_vgeo32 = nullptr, *d_fgeo32 = nullptr, *d_lam32 = nullptr, *d_tau32 = nullptr;
+    // per element [8]: G~ (00 01 02 11 12 22) and |J| of an affine (parallelepiped)
+    // element, zero otherwise; ElemDesc::pad bit AFFINE marks the affine elements
+    double *d_egeo64 = nullptr;
+    float *d_egeo32 = nullptr;
     double *d_tau0 = nullptr;
     double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it
     double *d_tbuf2 = nullptr;             // second trace buffer (gradients), lazy
@@ -129,6 +137,10 @@ struct sipdg_ctx {
     // stage run concurrently, joined back into the caller's stream
     std::vector<hipStream_t> gstreams;
     std::vector<hipEvent_t> gevents;   // [0] fork, [1 + g] group g done
+    // partly affine order groups: the affine part's apply launch runs on this
+    // side stream beside the deformed part's, so that their tails overlap
+    hipStream_t aff_stream = nullptr;
+    hipEvent_t aff_ev[2] = {nullptr, nullptr};   // fork, join
     bool concurrent = false;
     // persistent gather-fold launch: every element of the order <= 6 groups
     // (with traces <= 8 x 8), by decreasing order; ElemDesc::pad = order

@@ -115,6 +115,7 @@ struct Data {
     const R *__restrict__ x;
     R *__restrict__ y;
     R *__restrict__ tbuf;
+    const R *__restrict__ egeo;   // [ne][8]: G~ (00 01 02 11 12 22), |J| of affine elements
 };
 
 // Tables are read through the constant address space: the compiler may then
@@ -647,12 +648,58 @@ __device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, cons
     lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
 }
 
+// Pointwise terms of one column (q0, q1) = (a, b), in place:
+// u <- lambda w |J| u, d <- (w G~) d with d the reference gradient.
+// Deformed elements (AFF false) read the stored per-point factors, in chunks,
+// so that the loads of one chunk are in flight together.  Affine elements (the
+// paper's regular-element case, AFF true, launched apart so that neither
+// kernel carries the other's registers) have constant G~ and |J|: 7
+// per-element values, wave uniform, times the tensor GLL weight w_a w_b w_q.
+template <class R, int P, bool AFF>
+__device__ __forceinline__ void pointwise(const Data<R> &D, const ElemDesc &ed, int a, int b, R *u, R *d0, R *d1,
+                                          R *d2) {
+    constexpr int N = P + 2, NPTS = N * N * N;
+    const int64_t e = ed.e;
+    if constexpr (AFF) {
+        const ctab<R> eg = as_const(D.egeo) + 8 * e;
+        const ctab<R> W = as_const(D.tab) + tab_off_W(N);
+        const R G00 = eg[0], G01 = eg[1], G02 = eg[2], G11 = eg[3], G12 = eg[4], G22 = eg[5];
+        const R lamj = D.lam[e] * eg[6];
+        const R wab = D.tab[tab_off_W(N) + a] * D.tab[tab_off_W(N) + b];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const R w = wab * W[q];
+            const R c0 = w * d0[q], c1 = w * d1[q], c2 = w * d2[q];
+            u[q] = lamj * w * u[q];
+            d0[q] = G00 * c0 + G01 * c1 + G02 * c2;
+            d1[q] = G01 * c0 + G11 * c1 + G12 * c2;
+            d2[q] = G02 * c0 + G12 * c1 + G22 * c2;
+        }
+        return;
+    }
+    const R *__restrict__ vg = D.vgeo + ed.voff;
+    const R lam = D.lam[e];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const int p = a + N * (b + N * q);
+        const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
+        const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
+        const R wj = vg[6 * NPTS + p];
+        const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
+        u[q] = lam * wj * u[q];
+        d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
+        d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
+        d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
+        if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // MODE 1 (apply, two-stage): y = A x with both sides' (u, g) read from the
 //   trace buffer written by the trace stage (k3t_elem); orders 6 and 8 take
 //   their own (u, g) from their face values instead.
 // MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
 // One element: descriptor blk of A.desc / A.fdesc, LDS at smem_raw.
-template <class R, int P, int MODE>
+template <class R, int P, int MODE, bool AFF = false>
 __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
     constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
     (void)WG;
@@ -849,23 +896,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     if constexpr (MODE == 1) {
     // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
     // in chunks, so that the factor loads of one chunk are in flight together
-    if (col) {
-        const R *__restrict__ vg = D.vgeo + ed.voff;
-        const R lam = D.lam[e];
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            const int p = a + N * (b + N * q);
-            const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
-            const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
-            const R wj = vg[6 * NPTS + p];
-            const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
-            u[q] = lam * wj * u[q];
-            d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
-            d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
-            d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
-            if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-        }
-    }
+    if (col) pointwise<R, P, AFF>(D, ed, a, b, u, d0, d1, d2);
 
         // faces, both of one direction at a time: flux from the trace buffer,
         // lifted back to the face points, added to the pointwise terms.
@@ -941,23 +972,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     } else {
         // fused: as the two-stage apply, with the element's own traces from its
         // face values and the neighbours' evaluated here
-        if (col) {
-            const R *__restrict__ vg = D.vgeo + ed.voff;
-            const R lam = D.lam[e];
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                const int p = a + N * (b + N * q);
-                const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
-                const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
-                const R wj = vg[6 * NPTS + p];
-                const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
-                u[q] = lam * wj * u[q];
-                d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
-                d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
-                d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
-                if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-            }
-        }
+        if (col) pointwise<R, P, false>(D, ed, a, b, u, d0, d1, d2);
         R LA[4], LB[4];
         {
             const FaceU<R> fu2 = face_uniform<R>(meta, 2);
@@ -1291,7 +1306,7 @@ __global__ __launch_bounds__(W) void k3t_all(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;
-    switch (A.desc[i].pad) {
+    switch (A.desc[i].pad & ELEM_ORDER_MASK) {
     case 1: k3t_elem<R, 1>(A, D, i, smem_raw); break;
     case 2: k3t_elem<R, 2>(A, D, i, smem_raw); break;
     case 3: k3t_elem<R, 3>(A, D, i, smem_raw); break;
@@ -1319,13 +1334,14 @@ struct Occ {
     static constexpr int V = 2;
 };
 
-// One launch per order group: block b handles element b of the group.
-template <class R, int P, int MODE>
+// One launch per order group (and per affine / deformed part of it): block b
+// handles element b of A.desc.
+template <class R, int P, int MODE, bool AFF = false>
 __global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(Occ<R, P, MODE>::V))) void k3g(Args A,
                                                                                                          Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    k3g_elem<R, P, MODE>(A, D, blockIdx.x, smem_raw);
+    k3g_elem<R, P, MODE, AFF>(A, D, blockIdx.x, smem_raw);
 }
 
 // LDS of the persistent kernel: the largest order's.
@@ -1352,7 +1368,7 @@ __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(2))) void k3g
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     for (int i = blockIdx.x; i < A.count; i += gridDim.x) {
-        const int P = A.desc[i].pad;
+        const int P = A.desc[i].pad & ELEM_ORDER_MASK;
         switch (P) {
         case 1: gf_elem<R, 1, MODE>(A, D, i, smem_raw); break;
         case 2: gf_elem<R, 2, MODE>(A, D, i, smem_raw); break;

@@ -92,6 +92,8 @@ class SipdgOperator:
         nv, nb = ctypes.c_int64(), ctypes.c_int64()
         C.check(self._lib.sipdg_num_points(self._h, ctypes.byref(nv), ctypes.byref(nb)))
         self.n_volume_points, self.n_boundary_points = nv.value, nb.value
+        C.check(self._lib.sipdg_num_affine(self._h, ctypes.byref(n)))
+        self.n_affine = n.value   # elements whose apply uses per-element geometry
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod

@@ -162,11 +162,15 @@ def random_coefficients(mesh: Mesh, seed: int) -> np.ndarray:
     return rng.standard_normal(mesh.n_dofs)
 
 
-def affine_mesh(dim: int, N: int, seed: int, order=2, lam=1.0, sigma: float = 1.0) -> Mesh:
+def affine_mesh(dim: int, N: int, seed: int, order=2, lam=1.0, sigma: float = 1.0,
+                deform_frac: float = 0.0) -> Mesh:
     """Every element a parallelogram/parallelepiped: a tensor lattice with
     seeded non-uniform spacing per axis mapped by one global linear map with
     positive determinant.  Used where an exact polynomial reproduction is
-    expected (constant Jacobian per element)."""
+    expected (constant Jacobian per element).  ``deform_frac`` > 0 moves that
+    fraction of the interior vertices (drawn after the map, same generator) by
+    ``U[-0.1h, 0.1h]`` per coordinate before the map, so that the elements
+    around them are deformed and the rest stay affine."""
     rng = np.random.default_rng(seed)
     axes = []
     for _ in range(dim):
@@ -180,6 +184,11 @@ def affine_mesh(dim: int, N: int, seed: int, order=2, lam=1.0, sigma: float = 1.
     B = np.eye(dim) + rng.uniform(-0.25, 0.25, size=(dim, dim))
     if np.linalg.det(B) < 0:
         B[0] *= -1.0
+    if deform_frac > 0.0:
+        interior = np.all((lat > 0) & (lat < N), axis=1)
+        moved = interior & (rng.uniform(size=len(ids)) < deform_frac)
+        h = 1.0 / N
+        X = X + rng.uniform(-0.1 * h, 0.1 * h, size=X.shape) * moved[:, None]
     base.coords = np.ascontiguousarray(X @ B.T)
-    base.meta.update({"affine": True, "seed": seed})
+    base.meta.update({"affine": deform_frac == 0.0, "seed": seed})
     return base
