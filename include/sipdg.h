@@ -203,6 +203,22 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
 #define SIPDG_NUM_VARIANTS              6
 int sipdg_set_variant(sipdg_handle h, int variant);   /* EINVAL if not allowed */
 int sipdg_get_variant(sipdg_handle h, int *variant);
+
+/* Where the default gather-fold apply takes a deformed element's geometric
+ * factors G~ w = |J| J^-1 J^-T w and |J| w (Sec. 2.1):
+ *   STORED: the per-point values computed at create (7 per quadrature point;
+ *           the default, and what every other kernel structure reads).
+ *   MAP:    derived at every quadrature point from the element's trilinear
+ *           map (21 coefficients per element, stored at create): more
+ *           arithmetic, far fewer bytes, the trade-off of Sec. 5.1.
+ * Same operator to rounding (FP64 within a few ulp of STORED).  Affine
+ * elements always use their 7 per-element constants.  3-D only (EINVAL for
+ * MAP on a 2-D handle).  Captured CG iterations are captured again after a
+ * change. */
+#define SIPDG_GEOMETRY_STORED 0
+#define SIPDG_GEOMETRY_MAP 1
+int sipdg_set_geometry(sipdg_handle h, int source);
+int sipdg_get_geometry(sipdg_handle h, int *source);
 /* Time one FP64 application with every allowed variant (reps each, HIP
  * events on the stream) and keep the fastest.  ms_out (host,
  * [SIPDG_NUM_VARIANTS], may be

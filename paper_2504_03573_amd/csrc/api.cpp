@@ -146,6 +146,11 @@ static const R *egeo_of(const sipdg_ctx *c) {
     if constexpr (sizeof(R) == 8) return (const R *)c->d_egeo64;
     else return (const R *)c->d_egeo32;
 }
+template <class R>
+static const R *emap_of(const sipdg_ctx *c) {
+    if constexpr (sizeof(R) == 8) return (const R *)c->d_emap64;
+    else return (const R *)c->d_emap32;
+}
 
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
@@ -160,7 +165,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, c->d_pdesc, c->d_pfdesc};
-                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                 rec_mark(rec, stage, -1, false, st);
                 hipError_t e = launch_gfold3d_persistent<R>(stage == 1 ? 0 : 1, c->num_cu * c->blocks_per_cu, A, D, st);
                 rec_mark(rec, stage, -1, true, st);
@@ -179,7 +184,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                     fast_args<R>(c, g, x, y, tbuf, skip, false, A3, D3);
                     g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
                                A3.toff, A3.skip, g.d_desc, g.d_fdesc};
-                    g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
+                    g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                     e = launch_gfold3d<R>(g.P, stage == 1 ? 0 : 1, g.nfmax, A, D, st);
                 } else {
                     OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
@@ -212,7 +217,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, c->d_pdesc, c->d_pfdesc};
-                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                 rec_mark(rec, stage, -1, false, main_st);
                 hipError_t e = launch_gfold3d_trace_all<R>(A, D, main_st);
                 rec_mark(rec, stage, -1, true, main_st);
@@ -251,7 +256,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
                 g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, g.d_desc, g.d_fdesc};
-                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c)};
+                g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                 rec_mark(rec, stage, (int)gi, false, st);
                 hipError_t e = hipSuccess;
                 if (mode == 1 && g.split) {
@@ -275,14 +280,14 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                             return fail(SIPDG_EHIP, "event record / wait (affine fork)");
                     }
                     e = launch_gfold3d<R>(g.P, 3, g.nfmax, Aa, D, side ? c->aff_stream : st);
-                    if (e == hipSuccess) e = launch_gfold3d<R>(g.P, 1, g.nfmax, Ad, D, st);
+                    if (e == hipSuccess) e = launch_gfold3d<R>(g.P, c->geo_map ? 4 : 1, g.nfmax, Ad, D, st);
                     if (side) {
                         if (hipEventRecord(c->aff_ev[1], c->aff_stream) != hipSuccess ||
                             hipStreamWaitEvent(st, c->aff_ev[1], 0) != hipSuccess)
                             return fail(SIPDG_EHIP, "event record / wait (affine join)");
                     }
                 } else {
-                    e = launch_gfold3d<R>(g.P, mode, g.nfmax, A, D, st);
+                    e = launch_gfold3d<R>(g.P, mode == 1 && c->geo_map ? 4 : mode, g.nfmax, A, D, st);
                 }
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
@@ -380,7 +385,7 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_corners, c->d_tab64, c->d_tab32, c->d_vgeo64, c->d_fgeo64, c->d_lam64,
                     c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
-                    c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32};
+                    c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->d_pdesc) (void)hipFree(c->d_pdesc);
@@ -526,6 +531,28 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         TRY(upload(&c->d_egeo64, eg));
         TRY(dalloc(&c->d_egeo32, (int64_t)eg.size()));
         TRYHIP(launch_cast_f32(c->d_egeo64, c->d_egeo32, (int64_t)eg.size(), 0));
+    }
+    // trilinear map per element: x(xi) = sum_S c_S prod_{k in S} xi_k with
+    // c_S = 1/8 sum_v X_v prod_{k in S} s_k(v), s_k(v) = +1 if bit k of v else -1;
+    // stored c1..c7 = S {0}, {1}, {2}, {0,1}, {0,2}, {1,2}, {0,1,2}
+    if (T.dim == 3) {
+        static const int SUB[7] = {1, 2, 4, 3, 5, 6, 7};   // bit masks of S
+        std::vector<double> cm((size_t)std::max<int64_t>(T.ne, 1) * 24, 0.0);
+        for (int64_t e = 0; e < T.ne; ++e) {
+            const double *X = &T.corners[(size_t)e * 24];
+            for (int i = 0; i < 7; ++i)
+                for (int a = 0; a < 3; ++a) {
+                    double t = 0.0;
+                    for (int v = 0; v < 8; ++v) {
+                        const int neg = __builtin_popcount(SUB[i] & ~v & 7) & 1;
+                        t += neg ? -X[v * 3 + a] : X[v * 3 + a];
+                    }
+                    cm[(size_t)e * 24 + 3 * i + a] = 0.125 * t;
+                }
+        }
+        TRY(upload(&c->d_emap64, cm));
+        TRY(dalloc(&c->d_emap32, (int64_t)cm.size()));
+        TRYHIP(launch_cast_f32(c->d_emap64, c->d_emap32, (int64_t)cm.size(), 0));
     }
     TRY(upload(&c->d_tau0, T.tau0));
     {
@@ -1013,6 +1040,21 @@ int sipdg_set_variant(sipdg_handle h, int variant) {
         return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
     }
     h->variant = variant;
+    return SIPDG_OK;
+}
+
+int sipdg_set_geometry(sipdg_handle h, int source) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (source != SIPDG_GEOMETRY_STORED && source != SIPDG_GEOMETRY_MAP)
+        return fail(SIPDG_EINVAL, "unknown geometry source");
+    if (source == SIPDG_GEOMETRY_MAP && h->dim != 3) return fail(SIPDG_EINVAL, "geometry from the map needs a 3-D mesh");
+    h->geo_map = source == SIPDG_GEOMETRY_MAP;
+    return SIPDG_OK;
+}
+
+int sipdg_get_geometry(sipdg_handle h, int *source) {
+    if (!h || !source) return fail(SIPDG_EINVAL, "null argument");
+    *source = h->geo_map ? SIPDG_GEOMETRY_MAP : SIPDG_GEOMETRY_STORED;
     return SIPDG_OK;
 }
 

@@ -124,6 +124,11 @@ struct sipdg_ctx {
     // element, zero otherwise; ElemDesc::pad bit AFFINE marks the affine elements
     double *d_egeo64 = nullptr;
     float *d_egeo32 = nullptr;
+    // per element [24]: trilinear map coefficients c1..c7 (x, y, z) and a pad
+    // (3-D), for the apply's on-the-fly geometry of deformed elements
+    double *d_emap64 = nullptr;
+    float *d_emap32 = nullptr;
+    bool geo_map = false;   // deformed elements: geometry from the map, not the stored factors
     double *d_tau0 = nullptr;
     double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it
     double *d_tbuf2 = nullptr;             // second trace buffer (gradients), lazy

@@ -116,6 +116,7 @@ struct Data {
     R *__restrict__ y;
     R *__restrict__ tbuf;
     const R *__restrict__ egeo;   // [ne][8]: G~ (00 01 02 11 12 22), |J| of affine elements
+    const R *__restrict__ emap;   // [ne][24]: trilinear map coefficients c1..c7 (x, y, z), pad
 };
 
 // Tables are read through the constant address space: the compiler may then
@@ -648,19 +649,82 @@ __device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, cons
     lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
 }
 
+// Where the apply takes an element's geometric factors from (a launch of
+// one kind covers elements of one kind).
+enum : int {
+    GEO_POINT = 0,    // stored per-point factors G~ w and |J| w
+    GEO_AFFINE = 1,   // affine element: 7 constants per element
+    GEO_MAP = 2,      // from the element's trilinear map, at every point
+};
+
 // Pointwise terms of one column (q0, q1) = (a, b), in place:
 // u <- lambda w |J| u, d <- (w G~) d with d the reference gradient.
-// Deformed elements (AFF false) read the stored per-point factors, in chunks,
-// so that the loads of one chunk are in flight together.  Affine elements (the
-// paper's regular-element case, AFF true, launched apart so that neither
-// kernel carries the other's registers) have constant G~ and |J|: 7
-// per-element values, wave uniform, times the tensor GLL weight w_a w_b w_q.
-template <class R, int P, bool AFF>
+// GEO_POINT reads the stored per-point factors, in chunks, so that the loads
+// of one chunk are in flight together.  GEO_AFFINE (the paper's regular
+// elements): constant G~ and |J|, 7 wave-uniform values per element, times the
+// tensor GLL weight w_a w_b w_q.  GEO_MAP (deformed elements, geometry derived
+// on the fly as the paper's design trades data for arithmetic): the
+// trilinear map x = c0 + c1 xi0 + c2 xi1 + c3 xi2 + c4 xi0 xi1 + c5 xi0 xi2 +
+// c6 xi1 xi2 + c7 xi0 xi1 xi2 gives, along the lane's column (xi0, xi1 fixed),
+// dx/dxi0 and dx/dxi1 linear in xi2 and dx/dxi2 constant; the rows of adj(J)
+// are the cross products of J's columns, G~ = adj adj^T / |J|.
+template <class R, int P, int GEO>
 __device__ __forceinline__ void pointwise(const Data<R> &D, const ElemDesc &ed, int a, int b, R *u, R *d0, R *d1,
                                           R *d2) {
     constexpr int N = P + 2, NPTS = N * N * N;
     const int64_t e = ed.e;
-    if constexpr (AFF) {
+    if constexpr (GEO == GEO_MAP) {
+        const ctab<R> cm = as_const(D.emap) + 24 * e;   // c1..c7, each (x, y, z)
+        const ctab<R> Xq = as_const(D.tab) + tab_off_X(N);
+        const ctab<R> W = as_const(D.tab) + tab_off_W(N);
+        const R xa = D.tab[tab_off_X(N) + a], xb = D.tab[tab_off_X(N) + b];
+        const R wab = D.tab[tab_off_W(N) + a] * D.tab[tab_off_W(N) + b];
+        const R lam = D.lam[e];
+        R A0[3], B0[3], A1[3], B1[3], J2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R c1 = cm[c], c2 = cm[3 + c], c3 = cm[6 + c], c4 = cm[9 + c];
+            const R c5 = cm[12 + c], c6 = cm[15 + c], c7 = cm[18 + c];
+            A0[c] = c1 + c4 * xb;
+            B0[c] = c5 + c7 * xb;
+            A1[c] = c2 + c4 * xa;
+            B1[c] = c6 + c7 * xa;
+            J2[c] = c3 + c5 * xa + (c6 + c7 * xa) * xb;
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const R z = Xq[q];
+            R j0[3], j1[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                j0[c] = A0[c] + B0[c] * z;
+                j1[c] = A1[c] + B1[c] * z;
+            }
+            // rows of adj(J): j1 x j2, j2 x j0, j0 x j1
+            const R r00 = j1[1] * J2[2] - j1[2] * J2[1], r01 = j1[2] * J2[0] - j1[0] * J2[2],
+                    r02 = j1[0] * J2[1] - j1[1] * J2[0];
+            const R r10 = J2[1] * j0[2] - J2[2] * j0[1], r11 = J2[2] * j0[0] - J2[0] * j0[2],
+                    r12 = J2[0] * j0[1] - J2[1] * j0[0];
+            const R r20 = j0[1] * j1[2] - j0[2] * j1[1], r21 = j0[2] * j1[0] - j0[0] * j1[2],
+                    r22 = j0[0] * j1[1] - j0[1] * j1[0];
+            const R det = j0[0] * r00 + j0[1] * r01 + j0[2] * r02;
+            const R w = wab * W[q];
+            const R s = w / det;
+            const R g00 = s * (r00 * r00 + r01 * r01 + r02 * r02);
+            const R g01 = s * (r00 * r10 + r01 * r11 + r02 * r12);
+            const R g02 = s * (r00 * r20 + r01 * r21 + r02 * r22);
+            const R g11 = s * (r10 * r10 + r11 * r11 + r12 * r12);
+            const R g12 = s * (r10 * r20 + r11 * r21 + r12 * r22);
+            const R g22 = s * (r20 * r20 + r21 * r21 + r22 * r22);
+            const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
+            u[q] = lam * (w * det) * u[q];
+            d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
+            d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
+            d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
+        }
+        return;
+    }
+    if constexpr (GEO == GEO_AFFINE) {
         const ctab<R> eg = as_const(D.egeo) + 8 * e;
         const ctab<R> W = as_const(D.tab) + tab_off_W(N);
         const R G00 = eg[0], G01 = eg[1], G02 = eg[2], G11 = eg[3], G12 = eg[4], G22 = eg[5];
@@ -699,7 +763,7 @@ __device__ __forceinline__ void pointwise(const Data<R> &D, const ElemDesc &ed, 
 //   their own (u, g) from their face values instead.
 // MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
 // One element: descriptor blk of A.desc / A.fdesc, LDS at smem_raw.
-template <class R, int P, int MODE, bool AFF = false>
+template <class R, int P, int MODE, int GEO = GEO_POINT>
 __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
     constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
     (void)WG;
@@ -896,7 +960,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     if constexpr (MODE == 1) {
     // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
     // in chunks, so that the factor loads of one chunk are in flight together
-    if (col) pointwise<R, P, AFF>(D, ed, a, b, u, d0, d1, d2);
+    if (col) pointwise<R, P, GEO>(D, ed, a, b, u, d0, d1, d2);
 
         // faces, both of one direction at a time: flux from the trace buffer,
         // lifted back to the face points, added to the pointwise terms.
@@ -972,7 +1036,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     } else {
         // fused: as the two-stage apply, with the element's own traces from its
         // face values and the neighbours' evaluated here
-        if (col) pointwise<R, P, false>(D, ed, a, b, u, d0, d1, d2);
+        if (col) pointwise<R, P, GEO_POINT>(D, ed, a, b, u, d0, d1, d2);
         R LA[4], LB[4];
         {
             const FaceU<R> fu2 = face_uniform<R>(meta, 2);
@@ -1336,12 +1400,12 @@ struct Occ {
 
 // One launch per order group (and per affine / deformed part of it): block b
 // handles element b of A.desc.
-template <class R, int P, int MODE, bool AFF = false>
+template <class R, int P, int MODE, int GEO = GEO_POINT>
 __global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(Occ<R, P, MODE>::V))) void k3g(Args A,
                                                                                                          Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    k3g_elem<R, P, MODE, AFF>(A, D, blockIdx.x, smem_raw);
+    k3g_elem<R, P, MODE, GEO>(A, D, blockIdx.x, smem_raw);
 }
 
 // LDS of the persistent kernel: the largest order's.

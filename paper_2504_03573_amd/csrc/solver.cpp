@@ -41,6 +41,7 @@ struct CgWork {
     hipGraphExec_t g64 = nullptr, g32 = nullptr;
     int gk64 = 0, gk32 = 0;
     int gpre64 = -1, gpre32 = -1;   // preconditioner flag the graph was captured with
+    int gop64 = -1, gop32 = -1;     // kernel structure and geometry source it was captured with
 };
 
 void free_cg(sipdg_ctx *c) {
@@ -176,8 +177,10 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
     hipGraphExec_t *gexec = sizeof(R) == 8 ? &w->g64 : &w->g32;
     int *gk = sizeof(R) == 8 ? &w->gk64 : &w->gk32;
     int *gpre = sizeof(R) == 8 ? &w->gpre64 : &w->gpre32;
+    int *gop = sizeof(R) == 8 ? &w->gop64 : &w->gop32;
     const int pre = o.precond != 0;
-    if (o.graph_k > 0 && maxit >= k && (*gexec == nullptr || *gk != k || *gpre != pre)) {
+    const int opk = 2 * c->variant + (c->geo_map ? 1 : 0);
+    if (o.graph_k > 0 && maxit >= k && (*gexec == nullptr || *gk != k || *gpre != pre || *gop != opk)) {
         if (*gexec) {
             (void)hipGraphExecDestroy(*gexec);
             *gexec = nullptr;
@@ -197,6 +200,7 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
         HIPCHK(ei);
         *gk = k;
         *gpre = pre;
+        *gop = opk;
     }
     int last_ckpt = 0;
     while (true) {

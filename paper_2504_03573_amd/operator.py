@@ -183,6 +183,19 @@ class SipdgOperator:
     def variant(self, name: str):
         C.check(self._lib.sipdg_set_variant(self._h, C.VARIANTS[name]))
 
+    @property
+    def geometry(self) -> str:
+        """Where the default apply takes deformed elements' geometric factors:
+        "stored" (per quadrature point, computed at create) or "map" (derived
+        at every point from the element's trilinear map)."""
+        v = ctypes.c_int()
+        C.check(self._lib.sipdg_get_geometry(self._h, ctypes.byref(v)))
+        return {b: a for a, b in C.GEOMETRY.items()}[v.value]
+
+    @geometry.setter
+    def geometry(self, name: str):
+        C.check(self._lib.sipdg_set_geometry(self._h, C.GEOMETRY[name]))
+
     def autotune(self, reps: int = 20, stream=None) -> dict:
         """Time every allowed kernel structure and keep the fastest."""
         ms = (ctypes.c_double * len(C.VARIANTS))()

@@ -120,6 +120,14 @@ def test_apply_parity(case):
     assert torch.equal(op.apply(xt), op.apply(xt))
     a, b = float(torch.dot(z, op.apply(xt))), float(torch.dot(xt, op.apply(z)))
     assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+    # deformed part from the trilinear map, affine part from its constants
+    op.geometry = "map"
+    try:
+        ym = op.apply(xt).cpu().numpy()
+        ym32 = op.apply(xt.float()).double().cpu().numpy()
+        assert rel(ym, y_ref) <= 1e-12 and rel(ym32, y_ref) <= 1e-5 and rel(ym, y) <= 1e-13
+    finally:
+        op.geometry = "stored"
 
 
 def test_variants_read_per_point(case):

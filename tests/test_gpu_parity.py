@@ -158,6 +158,36 @@ def test_cg_f32_ir(case):
     assert torch.equal(xg, xh) or info_g["iters"] == info_h["iters"]
 
 
+def test_geometry_map(case):
+    """Geometric factors derived at every point from the element's trilinear
+    map give the operator of the stored per-point factors (Sec. 5.1: data
+    traded for arithmetic), FP64 and FP32, and CG with captured iterations."""
+    name, mesh, op, om = case
+    if mesh.dim != 3:
+        with pytest.raises(P_error()):
+            op.geometry = "map"
+        return
+    x = synth.random_coefficients(mesh, 4006)
+    y_ref = om.apply(x)
+    xt = torch.tensor(x, device="cuda")
+    keep = op.variant
+    op.variant = "gather_fold"
+    try:
+        y_st = op.apply(xt).cpu().numpy()
+        op.geometry = "map"
+        assert op.geometry == "map"
+        y = op.apply(xt).cpu().numpy()
+        y32 = op.apply(xt.float()).double().cpu().numpy()
+        print(f"{name}: map fp64 {rel(y, y_ref):.2e} fp32 {rel(y32, y_ref):.2e}")
+        assert rel(y, y_ref) <= 1e-12 and rel(y32, y_ref) <= 1e-5
+        assert rel(y, y_st) <= 1e-13
+        xs, info = op.cg_solve(torch.tensor(y_ref, device="cuda"), tol=1e-10, graph_k=5)
+        assert info["converged"] and rel(xs.cpu().numpy(), x) <= 1e-6
+    finally:
+        op.geometry = "stored"
+        op.variant = keep
+
+
 def test_variants_agree(case):
     """Gather-and-interpolate and direct trace evaluation give the same
     operator (Sec. 3.2: equivalent when the trace order is at least the
