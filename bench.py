@@ -91,11 +91,11 @@ def kernel_name(variant, order, stage=2, geo_map=False):
     if variant == "gather_fold":
         if stage == 1:
             return "sipdg::g3::k3t_all<double>" if order == 0 else "sipdg::g3::k3t<double, %d>" % order
-        return "sipdg::g3::k3g<double, %d, 1%s>" % (order, ", 2" if geo_map else "")
+        return "sipdg::g3::k3g<double, %d, 1, %d>" % (order, 2 if geo_map else 0)
     if variant == "gather_fold_persistent" and order == 0:
         return "sipdg::g3::k3g_persistent<double, %d>" % (0 if stage == 1 else 1)
     if variant == "gather_fold_fused":
-        return "sipdg::g3::k3g<double, %d, 2>" % order
+        return "sipdg::g3::k3g<double, %d, 2, 0>" % order
     if variant == "two_stage":
         return ("sipdg::f3::k3_trace<double, %d>" % order if stage == 1
                 else "sipdg::f3::k3_apply<double, %d, false>" % order)

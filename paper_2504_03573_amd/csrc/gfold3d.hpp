@@ -1392,16 +1392,19 @@ __host__ __device__ constexpr int lds_mode(int mode) {
     return mode == 0 ? TSz<P>::TOTAL : lds_total<P>(mode);
 }
 
-// Waves per SIMD the compiler sizes the registers of a kernel for.
-template <class R, int P, int MODE>
+// Waves per SIMD the compiler sizes the registers of a kernel for.  The FP64
+// map-geometry applies of orders 3 and 4 fit 3 waves (168 VGPRs; order 4 with
+// a 60-byte spill) and gain 7 and 3 us on the 32^3 mesh; orders 5 and 6 spill
+// 132 and 204 bytes there and lose, so they stay at 2.
+template <class R, int P, int MODE, int GEO = GEO_POINT>
 struct Occ {
-    static constexpr int V = 2;
+    static constexpr int V = (GEO == GEO_MAP && sizeof(R) == 8 && (P == 3 || P == 4)) ? 3 : 2;
 };
 
 // One launch per order group (and per affine / deformed part of it): block b
 // handles element b of A.desc.
 template <class R, int P, int MODE, int GEO = GEO_POINT>
-__global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(Occ<R, P, MODE>::V))) void k3g(Args A,
+__global__ __launch_bounds__(Geo<P>::W) __attribute__((amdgpu_waves_per_eu(Occ<R, P, MODE, GEO>::V))) void k3g(Args A,
                                                                                                          Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
