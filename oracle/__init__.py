@@ -35,8 +35,11 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, OpenMP)."""
-    if force or not os.path.exists(_LIB_PATH):
+    """Compile ``oracle.c`` into ``liboracle.so`` (gcc, OpenMP); without
+    ``force`` only when the library is missing or older than the source."""
+    stale = (not os.path.exists(_LIB_PATH)
+             or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC))
+    if force or stale:
         cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99", _SRC,
                "-o", _LIB_PATH + ".tmp", "-lm"]
         subprocess.check_call(cmd)
@@ -73,6 +76,7 @@ def _load():
         P = ctypes.POINTER(_OMesh)
         vp, lp = ctypes.c_void_p, ctypes.c_long
         lib.oracle_apply.argtypes = [P, vp, vp, vp, lp]
+        lib.oracle_apply_p2p.argtypes = [P, vp, vp, vp, lp]
         lib.oracle_diagonal.argtypes = [P, vp]
         lib.oracle_points.argtypes = [P, vp, vp, vp, vp]
         lib.oracle_rhs.argtypes = [P, vp, vp, vp]
@@ -82,7 +86,7 @@ def _load():
         lib.oracle_face_moments.argtypes = [P, vp, vp]
         lib.oracle_num_threads.argtypes = []
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
-        for f in (lib.oracle_apply, lib.oracle_diagonal, lib.oracle_points, lib.oracle_rhs,
+        for f in (lib.oracle_apply, lib.oracle_apply_p2p, lib.oracle_diagonal, lib.oracle_points, lib.oracle_rhs,
                   lib.oracle_param_grad, lib.oracle_sample, lib.oracle_min_detj,
                   lib.oracle_face_moments, lib.oracle_num_threads, lib.oracle_set_num_threads):
             f.restype = ctypes.c_int
@@ -259,6 +263,20 @@ class OracleMesh:
             raise MemoryError("oracle_apply")
         return y
 
+    def apply_p2p(self, x: np.ndarray, elems=None) -> np.ndarray:
+        """y = A x with point-to-point interpolation on interior faces
+        (Sec. 3.3): each side integrates on its own face quadrature with the
+        other side's value and gradient interpolated to it."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.shape == (self.n_dofs,)
+        y = np.zeros(self.n_dofs)
+        el = None if elems is None else np.ascontiguousarray(elems, dtype=np.int64)
+        rc = _load().oracle_apply_p2p(ctypes.byref(self._s), x.ctypes.data, y.ctypes.data,
+                                      None if el is None else el.ctypes.data, 0 if el is None else len(el))
+        if rc:
+            raise MemoryError("oracle_apply_p2p")
+        return y
+
     def diagonal(self) -> np.ndarray:
         y = np.zeros(self.n_dofs)
         if _load().oracle_diagonal(ctypes.byref(self._s), y.ctypes.data):
@@ -335,14 +353,15 @@ class OracleMesh:
         return sn, ar
 
     # ------------------------------------------------------------ assembly / solve
-    def assemble(self) -> np.ndarray:
-        """Brute force: column j is A e_j."""
+    def assemble(self, flux: str = "shared") -> np.ndarray:
+        """Brute force: column j is A e_j (flux "shared" or "p2p")."""
         n = self.n_dofs
         A = np.zeros((n, n))
         e = np.zeros(n)
+        f = self.apply if flux == "shared" else self.apply_p2p
         for j in range(n):
             e[j] = 1.0
-            A[:, j] = self.apply(e)
+            A[:, j] = f(e)
             e[j] = 0.0
         return A
 

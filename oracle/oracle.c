@@ -214,7 +214,35 @@ static void trace_point(const omesh *m, int d, int nF, int t, double *z, double 
     else { int t1 = t % nF, t2 = t / nF; z[0] = gx[t1]; z[1] = gx[t2]; *w = gw[t1] * gw[t2]; }
 }
 
-enum { MODE_APPLY = 0, MODE_DIAG = 1 };
+enum { MODE_APPLY = 0, MODE_DIAG = 1, MODE_APPLY_P2P = 2 };
+
+/* Lagrange basis polynomial i of the n GLL nodes gx at z. */
+static double lagrange(int n, const double *gx, int i, double z)
+{
+    double v = 1.0;
+    for (int k = 0; k < n; ++k)
+        if (k != i) v *= (z - gx[k]) / (gx[i] - gx[k]);
+    return v;
+}
+
+/* Point-to-point interpolation (Sec. 3.3, ScatrInterp): the other side's value
+ * and physical gradient at its own face quadrature points (its GLL grid, in
+ * its face coordinates), Lagrange-interpolated to the point zn given in those
+ * coordinates.  F holds [nn^(d-1)][1 + d] samples. */
+static void interp_other(int d, int nn, const double *gx, const double *F, const double *zn,
+                         double *u, double *gu)
+{
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int np = d == 2 ? nn : nn * nn;
+    for (int t = 0; t < np; ++t) {
+        int t1 = t % nn, t2 = t / nn;
+        double l = lagrange(nn, gx, t1, zn[0]);
+        if (d == 3) l *= lagrange(nn, gx, t2, zn[1]);
+        for (int c = 0; c <= d; ++c) acc[c] += l * F[t * 4 + c];
+    }
+    *u = acc[0];
+    for (int c = 0; c < d; ++c) gu[c] = acc[1 + c];
+}
 
 /* Rows of element e of A x (mode APPLY) or of diag(A) (mode DIAG). */
 static void element_rows(const omesh *m, long e, const double *x, double *y, int mode,
@@ -237,7 +265,7 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
         element_map(m, e, xi, X, J);
         double det = invert(d, J, Ji);
         basis_at(d, p, xi, Ji, phi, gphi);
-        if (mode == MODE_APPLY) {
+        if (mode != MODE_DIAG) {
             double u, gu[3];
             field_at(d, nm, phi, gphi, xe, &u, gu);
             for (int i = 0; i < nm; ++i) {
@@ -263,9 +291,56 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
         int pn = nbr >= 0 ? m->order[nbr] : p;
         int pF = p > pn ? p : pn, nF = pF + 2;
         double tau = m->sigma * 2.0 * (pF + 1.0) * (pF + 1.0) / m->h;
-        int nt = (d == 2) ? nF : nF * nF;
         int nmn = nbr >= 0 ? ipow(pn + 1, d) : 0;
         const double *xn = (nbr >= 0 && x) ? x + m->dof_off[nbr] : NULL;
+        if (mode == MODE_APPLY_P2P && nbr >= 0) {
+            /* point to point: this side's own face quadrature (n = p + 2 GLL
+             * points per direction, its own weights and surface Jacobian);
+             * the neighbour's u and grad u sampled at its own face points and
+             * interpolated to ours; same penalty tau_F.  Face coordinates:
+             * the owner's are canonical, the other side's are A times them. */
+            int nn = pn + 2, npn = d == 2 ? nn : nn * nn, nown = d == 2 ? n : n * n;
+            const double *gxn = m->gll_x + nn * OR_MAXN;
+            double F[OR_MAXN * OR_MAXN * 4];
+            for (int t = 0; t < npn; ++t) {
+                double z[2], wz;
+                trace_point(m, d, nn, t, z, &wz);
+                side_geo gq;
+                side_geometry(m, nbr, fn, z, &gq);
+                basis_at(d, pn, gq.xi, gq.Ji, phn, gphn);
+                double un, gun[3] = {0.0, 0.0, 0.0};
+                field_at(d, nmn, phn, gphn, xn, &un, gun);
+                F[t * 4] = un;
+                for (int c = 0; c < d; ++c) F[t * 4 + 1 + c] = gun[c];
+            }
+            for (int t = 0; t < nown; ++t) {
+                double z[2], wz, c2[2], zn[2];
+                trace_point(m, d, n, t, z, &wz);
+                if (own) apply_amap(d, A, z, zn);
+                else {   /* canonical = A^T (own coordinates); the neighbour owns */
+                    if (d == 2) c2[0] = A[0] * z[0];
+                    else { c2[0] = A[0] * z[0] + A[2] * z[1]; c2[1] = A[1] * z[0] + A[3] * z[1]; }
+                    zn[0] = c2[0];
+                    zn[1] = d == 3 ? c2[1] : 0.0;
+                }
+                side_geo ge;
+                side_geometry(m, e, f, z, &ge);
+                double a = wz * ge.Js;
+                basis_at(d, p, ge.xi, ge.Ji, phi, gphi);
+                double ue, gue[3], un, gun[3] = {0.0, 0.0, 0.0};
+                field_at(d, nm, phi, gphi, xe, &ue, gue);
+                interp_other(d, nn, gxn, F, zn, &un, gun);
+                double jump = ue - un, avg = 0.0;
+                for (int c = 0; c < d; ++c) avg += 0.5 * (gue[c] + gun[c]) * ge.n[c];
+                for (int i = 0; i < nm; ++i) {
+                    double dn = 0.0;
+                    for (int c = 0; c < d; ++c) dn += gphi[i * 3 + c] * ge.n[c];
+                    ye[i] += a * (-0.5 * jump * dn - phi[i] * avg + tau * jump * phi[i]);
+                }
+            }
+            continue;
+        }
+        int nt = (d == 2) ? nF : nF * nF;
         for (int t = 0; t < nt; ++t) {
             double z[2], wz, zo[2], zn[2];
             trace_point(m, d, nF, t, z, &wz);
@@ -282,7 +357,7 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
                 a = wz * ge.Js;
             }
             basis_at(d, p, ge.xi, ge.Ji, phi, gphi);
-            if (mode == MODE_APPLY) {
+            if (mode != MODE_DIAG) {
                 double ue, gue[3], un, gun[3];
                 field_at(d, nm, phi, gphi, xe, &ue, gue);
                 if (nbr >= 0) {
@@ -321,9 +396,9 @@ static int max_modes(const omesh *m)
     return ipow(pm + 1, m->dim);
 }
 
-/* y = A x.  If elems != NULL only the rows of the listed elements are
- * written (the rest of y is untouched). */
-int oracle_apply(const omesh *m, const double *x, double *y, const long *elems, long nsel)
+/* Rows of A x for every element (or the listed ones) in the given mode. */
+static int apply_mode(const omesh *m, const double *x, double *y, const long *elems, long nsel,
+                      int mode)
 {
     int mm = max_modes(m);
     long cnt = elems ? nsel : m->ne;
@@ -338,12 +413,29 @@ int oracle_apply(const omesh *m, const double *x, double *y, const long *elems, 
 #pragma omp for schedule(dynamic, 4)
             for (long i = 0; i < cnt; ++i) {
                 long e = elems ? elems[i] : i;
-                element_rows(m, e, x, y, MODE_APPLY, buf, buf + mm, buf + 4 * mm, buf + 5 * mm);
+                element_rows(m, e, x, y, mode, buf, buf + mm, buf + 4 * mm, buf + 5 * mm);
             }
             free(buf);
         }
     }
     return bad ? -1 : 0;
+}
+
+/* y = A x.  If elems != NULL only the rows of the listed elements are
+ * written (the rest of y is untouched). */
+int oracle_apply(const omesh *m, const double *x, double *y, const long *elems, long nsel)
+{
+    return apply_mode(m, x, y, elems, nsel, MODE_APPLY);
+}
+
+/* y = A_p2p x: the same form with every interior face integrated twice,
+ * once per side on that side's own face quadrature with the other side's
+ * trace interpolated point to point (Sec. 3.3, point-to-point
+ * interpolation).  Boundary faces as in oracle_apply.  Not symmetric in
+ * general (Sec. 3.3 conditions; Table 2). */
+int oracle_apply_p2p(const omesh *m, const double *x, double *y, const long *elems, long nsel)
+{
+    return apply_mode(m, x, y, elems, nsel, MODE_APPLY_P2P);
 }
 
 /* diag(A): a(phi_i, phi_i) with every other coefficient zero (Jacobi). */
