@@ -215,6 +215,25 @@ int sipdg_get_variant(sipdg_handle h, int *variant);
  * elements always use their 7 per-element constants.  3-D only (EINVAL for
  * MAP on a 2-D handle).  Captured CG iterations are captured again after a
  * change. */
+/* Interface flux of interior faces:
+ *   SHARED: the shared trace space (Sec. 3.3): both sides evaluated at one
+ *           GLL set of max(p_L, p_R) + 2 points per direction; A symmetric.
+ *           The default, and the only flux of every other entry point.
+ *   P2P:    point-to-point interpolation (Sec. 3.3, ScatrInterp): each side
+ *           integrates on its own p + 2 GLL face points with the other
+ *           side's value and physical gradient Lagrange-interpolated to them.
+ *           Not symmetric in general (Sec. 3.3 conditions, Table 2).  3-D.
+ *           While set, only sipdg_apply, sipdg_apply_stage and
+ *           sipdg_apply_timed are allowed (default kernel structure ignored:
+ *           one trace and one apply launch per order group); CG, transpose,
+ *           diagonal, parameter gradients and autotuning return EINVAL.
+ *           The first switch allocates a buffer of 8 values per trace point
+ *           of each interior face side (EHIP if that fails). */
+#define SIPDG_FLUX_SHARED 0
+#define SIPDG_FLUX_P2P 1
+int sipdg_set_flux(sipdg_handle h, int flux);
+int sipdg_get_flux(sipdg_handle h, int *flux);
+
 #define SIPDG_GEOMETRY_STORED 0
 #define SIPDG_GEOMETRY_MAP 1
 int sipdg_set_geometry(sipdg_handle h, int source);

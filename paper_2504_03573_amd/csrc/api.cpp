@@ -74,6 +74,10 @@ OpArgs<R> make_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *tbu
     A.y = y;
     A.tbuf = tbuf;
     A.skip = skip;
+    A.order = c->d_order;
+    A.faces = c->d_faces;
+    if constexpr (sizeof(R) == 8) A.emap = (const R *)c->d_emap64;
+    else A.emap = (const R *)c->d_emap32;
     return A;
 }
 template OpArgs<double> make_args<double>(const sipdg_ctx *, const Group &, const double *, double *, double *, const int *);
@@ -155,6 +159,24 @@ static const R *emap_of(const sipdg_ctx *c) {
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
                LaunchRec *rec) {
+    if (c->flux == SIPDG_FLUX_P2P) {
+        // point-to-point flux: per order group, a trace launch (own face
+        // points) then an apply launch, on the handle's own buffer
+        R *pb = (R *)c->d_tbuf_p2p;
+        for (int stage = 1; stage <= 2; ++stage) {
+            if (!(stages & stage)) continue;
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
+                OpArgs<R> A = make_args<R>(c, g, x, y, pb, skip);
+                rec_mark(rec, stage, (int)gi, false, st);
+                hipError_t e = launch_p2p<R>(g.P, stage, A, st);
+                rec_mark(rec, stage, (int)gi, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string("point-to-point kernel: ") + hipGetErrorString(e));
+            }
+        }
+        return SIPDG_OK;
+    }
     if (c->variant == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT) {
         for (int stage = 1; stage <= 2; ++stage) {
             if (!(stages & stage)) continue;
@@ -385,7 +407,8 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_corners, c->d_tab64, c->d_tab32, c->d_vgeo64, c->d_fgeo64, c->d_lam64,
                     c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
-                    c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32};
+                    c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32,
+                    c->d_tbuf_p2p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->d_pdesc) (void)hipFree(c->d_pdesc);
@@ -889,7 +912,7 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
                 const Group &g = h->groups[gi];
                 info[i].order = g.P;
                 info[i].elements = g.count;
-                info[i].alg_bytes = info[i].stage == 2 ? g.alg_bytes[w] : 0.0;
+                info[i].alg_bytes = info[i].stage == 2 && h->flux == SIPDG_FLUX_SHARED ? g.alg_bytes[w] : 0.0;
             } else {
                 // the persistent launch: every group of order <= 6 with traces <= 8 x 8
                 info[i].order = 0;
@@ -907,12 +930,36 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
     return rc;
 }
 
+static const char *P2P_ONLY_APPLY =
+    "the point-to-point flux gives a nonsymmetric operator: only sipdg_apply, sipdg_apply_stage and "
+    "sipdg_apply_timed use it (set SIPDG_FLUX_SHARED for this call)";
+
 int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision, void *stream) {
+    if (h && h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
     return sipdg_apply(h, g, xbar, precision, stream);
+}
+
+int sipdg_set_flux(sipdg_handle h, int flux) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (flux != SIPDG_FLUX_SHARED && flux != SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, "unknown flux");
+    if (flux == SIPDG_FLUX_P2P) {
+        if (h->dim != 3) return fail(SIPDG_EINVAL, "the point-to-point flux needs a 3-D mesh");
+        if (!h->d_tbuf_p2p)
+            HIPCHK(hipMalloc(&h->d_tbuf_p2p, sizeof(double) * std::max<int64_t>(1, 2 * h->tbuf_len)));
+    }
+    h->flux = flux;
+    return SIPDG_OK;
+}
+
+int sipdg_get_flux(sipdg_handle h, int *flux) {
+    if (!h || !flux) return fail(SIPDG_EINVAL, "null argument");
+    *flux = h->flux;
+    return SIPDG_OK;
 }
 
 int sipdg_diagonal(sipdg_handle h, double *d, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
     if (h->ndof == 0) return SIPDG_OK;
     if (!d) return fail(SIPDG_EINVAL, "null argument");
     HIPCHK(hipMemcpyAsync(d, h->d_diag64, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -987,6 +1034,7 @@ int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *
 int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *dlam, double *dsig,
                      void *stream) {
     if (!h || !dsig) return fail(SIPDG_EINVAL, "null argument");
+    if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
     hipStream_t st = (hipStream_t)stream;
     if (h->ne == 0) {   // empty mesh: every problem's penalty gradient is zero
         HIPCHK(hipMemsetAsync(dsig, 0, sizeof(double) * h->nprob, st));
@@ -1066,6 +1114,7 @@ int sipdg_get_variant(sipdg_handle h, int *variant) {
 
 int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
     if (reps <= 0) reps = 20;
     hipStream_t st = (hipStream_t)stream;
     double *x = nullptr, *y = nullptr;

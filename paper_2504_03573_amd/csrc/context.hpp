@@ -54,6 +54,10 @@ struct OpArgs {
     R *y;
     R *tbuf;                // trace buffer
     const int *skip;        // optional: return at once when *skip != 0
+    // point-to-point flux (3-D) only
+    const int *order = nullptr;             // [ne]
+    const struct FaceTopo *faces = nullptr; // [nf]
+    const R *emap = nullptr;                // [ne][24] trilinear map coefficients
 };
 
 // Per-element descriptors of an order group (3-D), indexed by the position in
@@ -129,6 +133,8 @@ struct sipdg_ctx {
     double *d_emap64 = nullptr;
     float *d_emap32 = nullptr;
     bool geo_map = false;   // deformed elements: geometry from the map, not the stored factors
+    int flux = 0;           // SIPDG_FLUX_SHARED or SIPDG_FLUX_P2P
+    void *d_tbuf_p2p = nullptr;   // point-to-point trace buffer (FP64 units: 2 x tbuf_len)
     double *d_tau0 = nullptr;
     double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it
     double *d_tbuf2 = nullptr;             // second trace buffer (gradients), lazy

@@ -475,26 +475,16 @@ __global__ __launch_bounds__(BLOCK) void k_trace(OpArgs<R> A, int nfm) {
     for (int k = 0; k < DIM; ++k) faces_dir<R, DIM, P, FACE_TRACE>(A, k, sm, es, s_e, s_face, nel, nfm, 0);
 }
 
-// K2: y = A x for the elements of the group.
+// Volume pointwise terms plus the staged face contributions, in place:
+// U <- m = lambda w|J| u (+ face value terms), G <- q = G w grad_xi u (+ face
+// gradient terms).  The staging area S (at S_off) holds per local face f the
+// value-test and grad-test inputs at the element's own face points.
 template <class R, int DIM, int P>
-__global__ __launch_bounds__(BLOCK) void k_apply(OpArgs<R> A, int nfm) {
+__device__ __forceinline__ void pointwise_faces(const OpArgs<R> &A, R *sm, int es, const int *s_e, int nel,
+                                                int S_off) {
     using C = Cfg<DIM, P>;
     using Ly = Lay<DIM, P>;
-    constexpr int N = C::N, NP = C::NP, EPB = C::EPB, NPTS = C::NPTS, NQ = C::NQ;
-    if (A.skip && *A.skip) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *tabs = reinterpret_cast<R *>(smem_raw);
-    R *sm = tabs + C::TABPAD;
-    __shared__ int s_e[EPB];
-    __shared__ FaceRef s_face[EPB * 2 * DIM];
-    const int es = elem_stride<DIM, P>(A.tsz, true);
-    const int S_off = Ly::T + A.tsz;
-    const R *Bt = tabs, *Dt = tabs + N * NP;
-    const int nel = block_setup<R, DIM, P>(A, tabs, s_e, s_face);
-    element_fields<R, DIM, P>(A.x, A.xoff, Bt, Dt, sm, es, s_e, nel);
-    for (int k = 0; k < DIM; ++k) faces_dir<R, DIM, P, FACE_LIFT>(A, k, sm, es, s_e, s_face, nel, nfm, S_off);
-
-    // volume pointwise terms + face contributions, in place: U <- m, G <- q
+    constexpr int N = C::N, NPTS = C::NPTS, NQ = C::NQ;
     for (int it = threadIdx.x; it < nel * NPTS; it += BLOCK) {
         const int el = it / NPTS, q = it - el * NPTS;
         const int e = s_e[el];
@@ -561,6 +551,30 @@ __global__ __launch_bounds__(BLOCK) void k_apply(OpArgs<R> A, int nfm) {
         }
     }
     __syncthreads();
+
+}
+
+// K2: y = A x for the elements of the group.
+template <class R, int DIM, int P>
+__global__ __launch_bounds__(BLOCK) void k_apply(OpArgs<R> A, int nfm) {
+    using C = Cfg<DIM, P>;
+    using Ly = Lay<DIM, P>;
+    constexpr int N = C::N, NP = C::NP, EPB = C::EPB, NPTS = C::NPTS, NQ = C::NQ;
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *tabs = reinterpret_cast<R *>(smem_raw);
+    R *sm = tabs + C::TABPAD;
+    __shared__ int s_e[EPB];
+    __shared__ FaceRef s_face[EPB * 2 * DIM];
+    const int es = elem_stride<DIM, P>(A.tsz, true);
+    const int S_off = Ly::T + A.tsz;
+    const R *Bt = tabs, *Dt = tabs + N * NP;
+    const int nel = block_setup<R, DIM, P>(A, tabs, s_e, s_face);
+    element_fields<R, DIM, P>(A.x, A.xoff, Bt, Dt, sm, es, s_e, nel);
+    for (int k = 0; k < DIM; ++k) faces_dir<R, DIM, P, FACE_LIFT>(A, k, sm, es, s_e, s_face, nel, nfm, S_off);
+
+    // volume pointwise terms + face contributions, in place: U <- m, G <- q
+    pointwise_faces<R, DIM, P>(A, sm, es, s_e, nel, S_off);
 
     element_iproduct<R, DIM, P>(A.y, A.xoff, Bt, Dt, sm, es, s_e, nel);
 }

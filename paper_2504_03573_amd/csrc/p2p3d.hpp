@@ -1,0 +1,200 @@
+// Point-to-point interpolation flux on hexahedra (Xia & Moxey, Sec. 3.3,
+// ScatrInterp): the alternative to the shared trace space.  Every interior
+// face is integrated twice, once per side, each side on its own GLL face
+// quadrature (its own n = p+2 points per direction, weights and surface
+// Jacobian), with the other side's value and physical gradient Lagrange-
+// interpolated to its points.  The operator is not symmetric in general (the
+// conditions of Sec. 3.3; Table 2).
+//
+//   K1 (trace): per element, at its own face points of every interior face:
+//               u and grad_x u = J^-T grad_xi u into the point-to-point
+//               buffer, in the owner's (canonical) orientation on the side's
+//               own n x n grid (four values per point and side).
+//   K2 (apply): per element: volume terms; per face, at its own face points:
+//               own u, grad_x u; the neighbour's four values interpolated from
+//               its n_o x n_o grid (tensor Lagrange interpolation with the
+//               I(n_o -> n) tables; boundary faces: the mirrored values);
+//               flux of eq. IP with the own outward normal, weights and
+//               surface Jacobian, staged at the face points (no lift needed:
+//               the quadrature points are the element's own); IProduct.
+//
+// Geometry at face points comes from the element's trilinear map (its 21
+// coefficients): the columns of J, the rows of adj(J) as cross products of
+// the columns, the area-weighted outward normal s * adj row k.
+#pragma once
+
+#include "launch.hpp"
+#include "operator.hpp"
+
+namespace sipdg {
+
+// Columns of J = dx/dxi (J[c][k] = dx_c/dxi_k) at xi from the coefficients
+// c1..c7 (each x, y, z) of x = c0 + c1 xi0 + c2 xi1 + c3 xi2 + c4 xi0 xi1 +
+// c5 xi0 xi2 + c6 xi1 xi2 + c7 xi0 xi1 xi2; rows of adj(J) and det J.
+template <class R>
+__device__ __forceinline__ R map_adjugate(const R *cm, R x0, R x1, R x2, R r[3][3]) {
+    R j0[3], j1[3], j2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        j0[c] = cm[c] + cm[9 + c] * x1 + cm[12 + c] * x2 + cm[18 + c] * x1 * x2;
+        j1[c] = cm[3 + c] + cm[9 + c] * x0 + cm[15 + c] * x2 + cm[18 + c] * x0 * x2;
+        j2[c] = cm[6 + c] + cm[12 + c] * x0 + cm[15 + c] * x1 + cm[18 + c] * x0 * x1;
+    }
+    r[0][0] = j1[1] * j2[2] - j1[2] * j2[1];
+    r[0][1] = j1[2] * j2[0] - j1[0] * j2[2];
+    r[0][2] = j1[0] * j2[1] - j1[1] * j2[0];
+    r[1][0] = j2[1] * j0[2] - j2[2] * j0[1];
+    r[1][1] = j2[2] * j0[0] - j2[0] * j0[2];
+    r[1][2] = j2[0] * j0[1] - j2[1] * j0[0];
+    r[2][0] = j0[1] * j1[2] - j0[2] * j1[1];
+    r[2][1] = j0[2] * j1[0] - j0[0] * j1[2];
+    r[2][2] = j0[0] * j1[1] - j0[1] * j1[0];
+    return j0[0] * r[0][0] + j0[1] * r[0][1] + j0[2] * r[0][2];
+}
+
+// One face point of the element of block slot el: local face f = 2k + s,
+// own face coordinates (a, b).  Loads u and grad_xi u from the element's
+// fields in LDS and returns the point's geometry.
+template <class R, int P>
+struct P2PPoint {
+    R u, gx[3];     // value and physical gradient
+    R r[3][3], det; // rows of adj(J), det J
+    int q;          // element point index
+};
+
+template <class R, int P>
+__device__ __forceinline__ P2PPoint<R, P> p2p_point(const OpArgs<R> &A, const R *sm, int es, int e, int k, int s,
+                                                   int a, int b) {
+    using C = Cfg<3, P>;
+    using Ly = Lay<3, P>;
+    constexpr int N = C::N;
+    P2PPoint<R, P> pt;
+    pt.q = face_point<3, N>(k, s, a, b);
+    const int i0 = pt.q % N, i1 = (pt.q / N) % N, i2 = pt.q / (N * N);
+    const R *X = A.tab + tab_off_X(N);
+    pt.det = map_adjugate<R>(A.emap + (int64_t)24 * e, X[i0], X[i1], X[i2], pt.r);
+    pt.u = sm[Ly::U + pt.q];
+    const R d0 = sm[Ly::G + pt.q], d1 = sm[Ly::G + C::NPTS + pt.q], d2 = sm[Ly::G + 2 * C::NPTS + pt.q];
+    const R inv = R(1) / pt.det;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pt.gx[c] = (pt.r[0][c] * d0 + pt.r[1][c] * d1 + pt.r[2][c] * d2) * inv;
+    return pt;
+}
+
+// K1: u and grad_x u at the own face points of every interior face side.
+// Buffer: face F at 2 toff[F], side slot at + slot 4 nf^2, component c at
+// + c nf^2, canonical index on the side's own n x n grid.
+template <class R, int P>
+__global__ __launch_bounds__(BLOCK) void k_p2p_trace(OpArgs<R> A) {
+    using C = Cfg<3, P>;
+    constexpr int N = C::N, NFP = C::NFP;
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *tabs = reinterpret_cast<R *>(smem_raw);
+    R *sm = tabs + C::TABPAD;
+    __shared__ int s_e[C::EPB];
+    __shared__ FaceRef s_face[C::EPB * 6];
+    const int es = elem_stride<3, P>(A.tsz, false);
+    const int nel = block_setup<R, 3, P>(A, tabs, s_e, s_face);
+    element_fields<R, 3, P>(A.x, A.xoff, tabs, tabs + N * C::NP, sm, es, s_e, nel);
+    for (int it = threadIdx.x; it < nel * 6 * NFP; it += BLOCK) {
+        const int el = it / (6 * NFP);
+        const int r = it - el * 6 * NFP;
+        const int f = r / NFP, fp = r - f * NFP;
+        const FaceRef fr = s_face[el * 6 + f];
+        const int slot = face_slot(fr.info);
+        if (slot == 2) continue;
+        const int a = fp % N, b = fp / N;
+        const P2PPoint<R, P> pt = p2p_point<R, P>(A, sm + el * es, es, s_e[el], f / 2, f & 1, a, b);
+        const int nf = face_nf(fr.info), npf = nf * nf;
+        const int qc = canon_index(face_orient(fr.info), N, a, b);
+        R *tb = A.tbuf + 2 * A.toff[fr.F] + (int64_t)slot * 4 * npf;
+        tb[qc] = pt.u;
+        tb[npf + qc] = pt.gx[0];
+        tb[2 * npf + qc] = pt.gx[1];
+        tb[3 * npf + qc] = pt.gx[2];
+    }
+}
+
+// K2: y = A_p2p x for the elements of the group.
+template <class R, int P>
+__global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A) {
+    using C = Cfg<3, P>;
+    using Ly = Lay<3, P>;
+    constexpr int N = C::N, NP = C::NP, NFP = C::NFP, NQ = C::NQ;
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *tabs = reinterpret_cast<R *>(smem_raw);
+    R *sm = tabs + C::TABPAD;
+    __shared__ int s_e[C::EPB];
+    __shared__ FaceRef s_face[C::EPB * 6];
+    const int es = elem_stride<3, P>(A.tsz, true);
+    const int S_off = Ly::T + A.tsz;
+    const R *Bt = tabs, *Dt = tabs + N * NP;
+    const int nel = block_setup<R, 3, P>(A, tabs, s_e, s_face);
+    element_fields<R, 3, P>(A.x, A.xoff, Bt, Dt, sm, es, s_e, nel);
+    const R *W = A.tab + tab_off_W(N);
+    for (int it = threadIdx.x; it < nel * 6 * NFP; it += BLOCK) {
+        const int el = it / (6 * NFP);
+        const int r = it - el * 6 * NFP;
+        const int f = r / NFP, fp = r - f * NFP;
+        const int k = f / 2, s = f & 1;
+        const FaceRef fr = s_face[el * 6 + f];
+        const int slot = face_slot(fr.info);
+        const int a = fp % N, b = fp / N;
+        const P2PPoint<R, P> pt = p2p_point<R, P>(A, sm + el * es, es, s_e[el], k, s, a, b);
+        // area-weighted outward normal times the quadrature weight: w s adj row k
+        const R w = W[a] * W[b];
+        R an[3];
+        R js2 = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R v = s ? pt.r[k][c] : -pt.r[k][c];
+            js2 += v * v;
+            an[c] = w * v;
+        }
+        const R aw = w * sqrt(js2);   // w J_s
+        const R g = an[0] * pt.gx[0] + an[1] * pt.gx[1] + an[2] * pt.gx[2];
+        R un, go;
+        if (slot == 2) {
+            // mirrored exterior: u+ = -u-, grad u+ = grad u-
+            un = -pt.u;
+            go = g;
+        } else {
+            const FaceTopo ft = A.faces[fr.F];
+            const int nbr = slot == 0 ? ft.eR : ft.eL;
+            const int no = A.order[nbr] + 2;
+            const int nf = face_nf(fr.info), npf = nf * nf;
+            const R *src = A.tbuf + 2 * A.toff[fr.F] + (int64_t)(1 - slot) * 4 * npf;
+            const int qc = canon_index(face_orient(fr.info), N, a, b);
+            const int c1 = qc % N, c2 = qc / N;
+            const R *I = A.tab + tab_off_I(no, N);   // [N][no]
+            R acc[4] = {0, 0, 0, 0};
+            for (int j2 = 0; j2 < no; ++j2) {
+                const R l2 = I[c2 * no + j2];
+                for (int j1 = 0; j1 < no; ++j1) {
+                    const R l = l2 * I[c1 * no + j1];
+                    const int idx = j2 * no + j1;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] += l * src[c * npf + idx];
+                }
+            }
+            un = acc[0];
+            go = an[0] * acc[1] + an[1] * acc[2] + an[2] * acc[3];
+        }
+        const R jump = pt.u - un;
+        const R Fv = R(-0.5) * (g + go) + A.tau[fr.F] * aw * jump;
+        const R Fg = R(-0.5) * jump;
+        const R inv = R(1) / pt.det;
+        R *S = sm + el * es + S_off + f * NQ * NFP + fp;
+        S[0] = Fv;
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            S[(1 + m) * NFP] = Fg * (an[0] * pt.r[m][0] + an[1] * pt.r[m][1] + an[2] * pt.r[m][2]) * inv;
+    }
+    __syncthreads();
+    pointwise_faces<R, 3, P>(A, sm, es, s_e, nel, S_off);
+    element_iproduct<R, 3, P>(A.y, A.xoff, Bt, Dt, sm, es, s_e, nel);
+}
+
+}  // namespace sipdg

@@ -272,6 +272,8 @@ void sipdg_cg_default_opts(sipdg_cg_opts *o) {
 int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_opts *opts,
                    sipdg_cg_info *info, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->flux == SIPDG_FLUX_P2P)
+        return fail(SIPDG_EINVAL, "CG needs the symmetric shared-trace operator (the point-to-point flux is set)");
     sipdg_cg_opts o;
     if (opts) o = *opts;
     else sipdg_cg_default_opts(&o);

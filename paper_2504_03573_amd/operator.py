@@ -196,6 +196,19 @@ class SipdgOperator:
     def geometry(self, name: str):
         C.check(self._lib.sipdg_set_geometry(self._h, C.GEOMETRY[name]))
 
+    @property
+    def flux(self) -> str:
+        """Interior-face flux of apply: "shared" (shared trace space, the
+        default) or "p2p" (point-to-point interpolation; nonsymmetric, only
+        apply / apply_stage / apply_timed accept it)."""
+        v = ctypes.c_int()
+        C.check(self._lib.sipdg_get_flux(self._h, ctypes.byref(v)))
+        return {b: a for a, b in C.FLUX.items()}[v.value]
+
+    @flux.setter
+    def flux(self, name: str):
+        C.check(self._lib.sipdg_set_flux(self._h, C.FLUX[name]))
+
     def autotune(self, reps: int = 20, stream=None) -> dict:
         """Time every allowed kernel structure and keep the fastest."""
         ms = (ctypes.c_double * len(C.VARIANTS))()
