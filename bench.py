@@ -14,9 +14,10 @@ sin(pi x) sin(pi y) sin(pi z)), and the CPU oracle timed on a bounded sample
 of the same workload.  `geometry_map` repeats the application and the solves
 with deformed elements' geometric factors derived at every point from their
 trilinear maps instead of read from HBM (a variant of the method, reported
-beside the metric).
+beside the metric); `p2p` times the application with the point-to-point
+interpolation flux instead of the shared trace (the paper's alternative).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-map]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-map] [--no-p2p]
 """
 
 from __future__ import annotations
@@ -180,6 +181,8 @@ def main():
                     help="kept for the profiling commands (the 1 GiB copy always runs)")
     ap.add_argument("--variant", default=None,
                     help="kernel structure to use instead of the autotuner's choice (profiling runs)")
+    ap.add_argument("--no-p2p", action="store_true",
+                    help="skip the apply with the point-to-point interpolation flux")
     ap.add_argument("--no-map", action="store_true",
                     help="skip the apply with geometry derived from the element maps")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_hex32_p3to6.json"))
@@ -353,6 +356,23 @@ def main():
         out["geometry_map"] = gm
         op.geometry = "stored"
         op.variant = keep
+    if not args.no_p2p:
+        # the point-to-point interpolation flux (the paper's alternative to the
+        # shared trace space; a different, nonsymmetric operator): application
+        # only, reported beside the metric
+        op.flux = "p2p"
+        for _ in range(args.warmup):
+            op.apply(x, out=y)
+            op.apply(x32, out=y32)
+        ms_p = time_events(lambda: op.apply(x, out=y), args.steps, stream)
+        ms_p32 = time_events(lambda: op.apply(x32, out=y32), args.steps, stream)
+        lp = op.apply_timed(x, y, reps=max(10, min(args.steps, 100)), stream=stream)
+        out["p2p"] = {"value": ndof / (ms_p * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms_p,
+                      "fp32_value": ndof / (ms_p32 * 1e-3) / 1e9, "fp32_ms": ms_p32,
+                      "launches": [{"kernel": "sipdg::k_p2p_%s<double, %d>" % ("trace" if L["stage"] == 1 else "apply",
+                                                                                L["order"]), "ms": L["ms"]}
+                                   for L in lp]}
+        op.flux = "shared"
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, x_np)
     print(json.dumps(out))

@@ -169,7 +169,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 const Group &g = c->groups[gi];
                 OpArgs<R> A = make_args<R>(c, g, x, y, pb, skip);
                 rec_mark(rec, stage, (int)gi, false, st);
-                hipError_t e = launch_p2p<R>(g.P, stage, A, st);
+                hipError_t e = launch_p2p<R>(g.P, stage, A, g.nfmax, st);
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
                     return fail(SIPDG_EHIP, std::string("point-to-point kernel: ") + hipGetErrorString(e));

@@ -5,11 +5,11 @@
 namespace sipdg {
 
 template <class R>
-hipError_t launch_p2p(int P, int stage, const OpArgs<R> &A, hipStream_t st);
+hipError_t launch_p2p(int P, int stage, const OpArgs<R> &A, int nfm, hipStream_t st);
 
 namespace {
 template <class R, int P>
-hipError_t p2p_p(int stage, const OpArgs<R> &A, hipStream_t st) {
+hipError_t p2p_p(int stage, const OpArgs<R> &A, int nfm, hipStream_t st) {
     using C = Cfg<3, P>;
     if (A.count <= 0) return hipSuccess;
     const int blocks = (A.count + C::EPB - 1) / C::EPB;
@@ -19,22 +19,22 @@ hipError_t p2p_p(int stage, const OpArgs<R> &A, hipStream_t st) {
         hipLaunchKernelGGL((k_p2p_trace<R, P>), dim3(blocks), dim3(BLOCK), lds, st, A);
     } else {
         ensure_lds(k_p2p_apply<R, P>, lds);
-        hipLaunchKernelGGL((k_p2p_apply<R, P>), dim3(blocks), dim3(BLOCK), lds, st, A);
+        hipLaunchKernelGGL((k_p2p_apply<R, P>), dim3(blocks), dim3(BLOCK), lds, st, A, nfm);
     }
     return hipGetLastError();
 }
 }  // namespace
 
 template <>
-hipError_t launch_p2p<double>(int P, int stage, const OpArgs<double> &A, hipStream_t st) {
-#define CALL(p) p2p_p<double, p>(stage, A, st)
+hipError_t launch_p2p<double>(int P, int stage, const OpArgs<double> &A, int nfm, hipStream_t st) {
+#define CALL(p) p2p_p<double, p>(stage, A, nfm, st)
     SIPDG_DISPATCH_P(P, CALL)
 #undef CALL
 }
 
 template <>
-hipError_t launch_p2p<float>(int P, int stage, const OpArgs<float> &A, hipStream_t st) {
-#define CALL(p) p2p_p<float, p>(stage, A, st)
+hipError_t launch_p2p<float>(int P, int stage, const OpArgs<float> &A, int nfm, hipStream_t st) {
+#define CALL(p) p2p_p<float, p>(stage, A, nfm, st)
     SIPDG_DISPATCH_P(P, CALL)
 #undef CALL
 }

@@ -10,9 +10,10 @@ enum OpKind { OP_TRACE = 0, OP_APPLY = 1 };
 // Operator kernels for one order group.  tsz must be work_size(nfm).
 template <class R>
 hipError_t launch_op(int dim, int P, int kind, const OpArgs<R> &A, int nfm, hipStream_t st);
-// Point-to-point flux kernels (3-D) for one order group: stage 1 trace, 2 apply.
+// Point-to-point flux kernels (3-D) for one order group: stage 1 trace, 2 apply;
+// tsz must be work_size(nfm).
 template <class R>
-hipError_t launch_p2p(int P, int stage, const OpArgs<R> &A, hipStream_t st);
+hipError_t launch_p2p(int P, int stage, const OpArgs<R> &A, int nfm, hipStream_t st);
 int work_size_for(int dim, int P, int nfm);
 size_t lds_for(int dim, int P, int tsz, bool lift, size_t rsize);
 int elems_per_block(int dim, int P);

@@ -10,13 +10,14 @@
 //               u and grad_x u = J^-T grad_xi u into the point-to-point
 //               buffer, in the owner's (canonical) orientation on the side's
 //               own n x n grid (four values per point and side).
-//   K2 (apply): per element: volume terms; per face, at its own face points:
-//               own u, grad_x u; the neighbour's four values interpolated from
-//               its n_o x n_o grid (tensor Lagrange interpolation with the
-//               I(n_o -> n) tables; boundary faces: the mirrored values);
-//               flux of eq. IP with the own outward normal, weights and
-//               surface Jacobian, staged at the face points (no lift needed:
-//               the quadrature points are the element's own); IProduct.
+//   K2 (apply): per element: volume terms; per face direction, both faces:
+//               the neighbour's four values interpolated from its n_o x n_o
+//               grid to ours, one direction at a time in LDS (I(n_o -> n)
+//               tables), and mapped to our face point order; then at our own
+//               face points the flux of eq. IP with our outward normal,
+//               weights and surface Jacobian (boundary faces: the mirrored
+//               values), staged at the face points (no lift needed: the
+//               quadrature points are the element's own); IProduct.
 //
 // Geometry at face points comes from the element's trilinear map (its 21
 // coefficients): the columns of J, the rows of adj(J) as cross products of
@@ -116,9 +117,20 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_trace(OpArgs<R> A) {
     }
 }
 
-// K2: y = A_p2p x for the elements of the group.
+// Own face coordinates (a, b) of canonical index qc on an n x n grid (the
+// inverse of canon_index for orientation code o).
+__device__ __forceinline__ int own_of_canon(int o, int n, int qc) {
+    const int c1 = qc % n, c2 = qc / n;
+    const int a1 = (o & 4) ? c2 : c1, a2 = (o & 4) ? c1 : c2;
+    const int r1 = (o & 1) ? n - 1 - a1 : a1;
+    const int r2 = (o & 2) ? n - 1 - a2 : a2;
+    return r1 + n * r2;
+}
+
+// K2: y = A_p2p x for the elements of the group (nfm: the group's largest
+// trace, which bounds every neighbour's n_o).
 template <class R, int P>
-__global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A) {
+__global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A, int nfm) {
     using C = Cfg<3, P>;
     using Ly = Lay<3, P>;
     constexpr int N = C::N, NP = C::NP, NFP = C::NFP, NQ = C::NQ;
@@ -134,63 +146,94 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A) {
     const int nel = block_setup<R, 3, P>(A, tabs, s_e, s_face);
     element_fields<R, 3, P>(A.x, A.xoff, Bt, Dt, sm, es, s_e, nel);
     const R *W = A.tab + tab_off_W(N);
-    for (int it = threadIdx.x; it < nel * 6 * NFP; it += BLOCK) {
-        const int el = it / (6 * NFP);
-        const int r = it - el * 6 * NFP;
-        const int f = r / NFP, fp = r - f * NFP;
-        const int k = f / 2, s = f & 1;
-        const FaceRef fr = s_face[el * 6 + f];
-        const int slot = face_slot(fr.info);
-        const int a = fp % N, b = fp / N;
-        const P2PPoint<R, P> pt = p2p_point<R, P>(A, sm + el * es, es, s_e[el], k, s, a, b);
-        // area-weighted outward normal times the quadrature weight: w s adj row k
-        const R w = W[a] * W[b];
-        R an[3];
-        R js2 = 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const R v = s ? pt.r[k][c] : -pt.r[k][c];
-            js2 += v * v;
-            an[c] = w * v;
-        }
-        const R aw = w * sqrt(js2);   // w J_s
-        const R g = an[0] * pt.gx[0] + an[1] * pt.gx[1] + an[2] * pt.gx[2];
-        R un, go;
-        if (slot == 2) {
-            // mirrored exterior: u+ = -u-, grad u+ = grad u-
-            un = -pt.u;
-            go = g;
-        } else {
+    const int fs = 4 * nfm * N;   // work-area floats per face side of one direction
+    for (int k = 0; k < 3; ++k) {
+        // P1: the neighbour's grid interpolated along the first canonical
+        // direction to our N points (work area: [s][c][j2][t1])
+        for (int it = threadIdx.x; it < nel * 2 * fs; it += BLOCK) {
+            const int el = it / (2 * fs);
+            int r = it - el * 2 * fs;
+            const int s = r / fs;
+            r -= s * fs;
+            const int c = r / (nfm * N);
+            r -= c * nfm * N;
+            const int j2 = r / N, t1 = r - j2 * N;
+            const FaceRef fr = s_face[el * 6 + 2 * k + s];
+            const int slot = face_slot(fr.info);
+            if (slot == 2) continue;
             const FaceTopo ft = A.faces[fr.F];
-            const int nbr = slot == 0 ? ft.eR : ft.eL;
-            const int no = A.order[nbr] + 2;
+            const int no = A.order[slot == 0 ? ft.eR : ft.eL] + 2;
+            if (j2 >= no) continue;
             const int nf = face_nf(fr.info), npf = nf * nf;
-            const R *src = A.tbuf + 2 * A.toff[fr.F] + (int64_t)(1 - slot) * 4 * npf;
-            const int qc = canon_index(face_orient(fr.info), N, a, b);
-            const int c1 = qc % N, c2 = qc / N;
-            const R *I = A.tab + tab_off_I(no, N);   // [N][no]
-            R acc[4] = {0, 0, 0, 0};
-            for (int j2 = 0; j2 < no; ++j2) {
-                const R l2 = I[c2 * no + j2];
-                for (int j1 = 0; j1 < no; ++j1) {
-                    const R l = l2 * I[c1 * no + j1];
-                    const int idx = j2 * no + j1;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c] += l * src[c * npf + idx];
-                }
-            }
-            un = acc[0];
-            go = an[0] * acc[1] + an[1] * acc[2] + an[2] * acc[3];
+            const R *src = A.tbuf + 2 * A.toff[fr.F] + (int64_t)(1 - slot) * 4 * npf + c * npf + j2 * no;
+            const R *I = A.tab + tab_off_I(no, N) + t1 * no;
+            R acc = 0;
+            for (int j1 = 0; j1 < no; ++j1) acc += I[j1] * src[j1];
+            sm[el * es + Ly::T + s * fs + (c * nfm + j2) * N + t1] = acc;
         }
-        const R jump = pt.u - un;
-        const R Fv = R(-0.5) * (g + go) + A.tau[fr.F] * aw * jump;
-        const R Fg = R(-0.5) * jump;
-        const R inv = R(1) / pt.det;
-        R *S = sm + el * es + S_off + f * NQ * NFP + fp;
-        S[0] = Fv;
+        __syncthreads();
+        // P2: along the second direction, stored at our own face point order
+        for (int it = threadIdx.x; it < nel * 2 * 4 * NFP; it += BLOCK) {
+            const int el = it / (8 * NFP);
+            int r = it - el * 8 * NFP;
+            const int s = r / (4 * NFP);
+            r -= s * 4 * NFP;
+            const int c = r / NFP, qc = r - c * NFP;
+            const FaceRef fr = s_face[el * 6 + 2 * k + s];
+            const int slot = face_slot(fr.info);
+            if (slot == 2) continue;
+            const FaceTopo ft = A.faces[fr.F];
+            const int no = A.order[slot == 0 ? ft.eR : ft.eL] + 2;
+            const int t1 = qc % N, t2 = qc / N;
+            const R *I = A.tab + tab_off_I(no, N) + t2 * no;
+            const R *tmp = sm + el * es + Ly::T + s * fs + c * nfm * N + t1;
+            R acc = 0;
+            for (int j2 = 0; j2 < no; ++j2) acc += I[j2] * tmp[j2 * N];
+            const int fp = own_of_canon(face_orient(fr.info), N, qc);
+            sm[el * es + S_off + ((2 * k + s) * NQ + c) * NFP + fp] = acc;
+        }
+        __syncthreads();
+        // P3: flux of eq. IP at our own face points, staged in place
+        for (int it = threadIdx.x; it < nel * 2 * NFP; it += BLOCK) {
+            const int el = it / (2 * NFP);
+            int r = it - el * 2 * NFP;
+            const int s = r / NFP, fp = r - s * NFP;
+            const int f = 2 * k + s;
+            const FaceRef fr = s_face[el * 6 + f];
+            const int slot = face_slot(fr.info);
+            const int a = fp % N, b = fp / N;
+            const P2PPoint<R, P> pt = p2p_point<R, P>(A, sm + el * es, es, s_e[el], k, s, a, b);
+            // area-weighted outward normal times the quadrature weight: w s adj row k
+            const R w = W[a] * W[b];
+            R an[3];
+            R js2 = 0;
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
-            S[(1 + m) * NFP] = Fg * (an[0] * pt.r[m][0] + an[1] * pt.r[m][1] + an[2] * pt.r[m][2]) * inv;
+            for (int c = 0; c < 3; ++c) {
+                const R v = s ? pt.r[k][c] : -pt.r[k][c];
+                js2 += v * v;
+                an[c] = w * v;
+            }
+            const R aw = w * sqrt(js2);   // w J_s
+            const R g = an[0] * pt.gx[0] + an[1] * pt.gx[1] + an[2] * pt.gx[2];
+            R *S = sm + el * es + S_off + f * NQ * NFP + fp;
+            R un, go;
+            if (slot == 2) {
+                // mirrored exterior: u+ = -u-, grad u+ = grad u-
+                un = -pt.u;
+                go = g;
+            } else {
+                un = S[0];
+                go = an[0] * S[NFP] + an[1] * S[2 * NFP] + an[2] * S[3 * NFP];
+            }
+            const R jump = pt.u - un;
+            const R Fv = R(-0.5) * (g + go) + A.tau[fr.F] * aw * jump;
+            const R Fg = R(-0.5) * jump;
+            const R inv = R(1) / pt.det;
+            S[0] = Fv;
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                S[(1 + m) * NFP] = Fg * (an[0] * pt.r[m][0] + an[1] * pt.r[m][1] + an[2] * pt.r[m][2]) * inv;
+        }
     }
     __syncthreads();
     pointwise_faces<R, 3, P>(A, sm, es, s_e, nel, S_off);

@@ -60,6 +60,24 @@ def test_workload_sampled_rows(env, k):
         assert np.linalg.norm(y[rows] - y_ref[rows]) <= 1e-12 * np.linalg.norm(y_ref[rows]), v
     y32 = op.apply(torch.tensor(x, device="cuda", dtype=torch.float32)).double().cpu().numpy()
     assert np.linalg.norm(y32[rows] - y_ref[rows]) <= 1e-5 * np.linalg.norm(y_ref[rows])
+    # geometry from the element maps, same rows
+    op.variant = "gather_fold"
+    op.geometry = "map"
+    try:
+        y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(y[rows] - y_ref[rows]) <= 1e-12 * np.linalg.norm(y_ref[rows])
+    finally:
+        op.geometry = "stored"
+    # point-to-point flux against the oracle's, same rows
+    yp_ref = om.apply_p2p(x, elems=elems)
+    op.flux = "p2p"
+    try:
+        y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(y[rows] - yp_ref[rows]) <= 1e-12 * np.linalg.norm(yp_ref[rows])
+        y32 = op.apply(torch.tensor(x, device="cuda", dtype=torch.float32)).double().cpu().numpy()
+        assert np.linalg.norm(y32[rows] - yp_ref[rows]) <= 1e-5 * np.linalg.norm(yp_ref[rows])
+    finally:
+        op.flux = "shared"
     # properties at full size: symmetry and determinism
     rng2 = np.random.default_rng(20 + k)
     a = torch.tensor(rng2.standard_normal(op.n_dofs), device="cuda")
