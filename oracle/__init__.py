@@ -31,6 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 OR_MAXN = 16
+BASES = {"legendre": 0, "modal": 1}
 _lib = None
 
 
@@ -64,6 +65,7 @@ class _OMesh(ctypes.Structure):
         ("amap", ctypes.c_void_p),
         ("gll_x", ctypes.c_void_p),
         ("gll_w", ctypes.c_void_p),
+        ("basis", ctypes.c_int),
     ]
 
 
@@ -173,8 +175,9 @@ def _face_corner_ids(ev_e: np.ndarray, dim: int, f: int):
 class OracleMesh:
     """A mesh prepared for the oracle (neighbours, owners, face maps)."""
 
-    def __init__(self, mesh):
+    def __init__(self, mesh, basis: str = "legendre"):
         self.mesh = mesh
+        self.basis = basis
         d = mesh.dim
         ne = mesh.n_elems
         nf = 2 * d
@@ -236,7 +239,8 @@ class OracleMesh:
             dof_off=self.dof_off.ctypes.data, h=float(mesh.h), sigma=float(mesh.sigma),
             nb=self.nb.ctypes.data, nb_face=self.nb_face.ctypes.data,
             owner=self.owner.ctypes.data, amap=self.amap.ctypes.data,
-            gll_x=_GLL_X.ctypes.data, gll_w=_GLL_W.ctypes.data)
+            gll_x=_GLL_X.ctypes.data, gll_w=_GLL_W.ctypes.data,
+            basis=BASES[basis])
 
     def set_lambda(self, lam):
         self.lam[:] = np.asarray(lam, dtype=np.float64)
@@ -396,5 +400,6 @@ class OracleMesh:
         return x, it, float(np.linalg.norm(b - self.apply(x))) / nb
 
 
-def prepare(mesh) -> OracleMesh:
-    return OracleMesh(mesh)
+def prepare(mesh, basis: str = "legendre") -> OracleMesh:
+    """basis: "legendre" (orthogonal) or "modal" (modified C0, Table 1)."""
+    return OracleMesh(mesh, basis)

@@ -9,8 +9,8 @@
  *
  * What it computes (Xia & Moxey, arXiv 2504.03573):
  *   - element expansion u = sum_j phi_j(xi) u_j, tensor-product bases
- *     (Sec. 2.1, expansion eq. and tensor basis eq.), here the orthogonal
- *     (Legendre) basis of Table 1;
+ *     (Sec. 2.1, expansion eq. and tensor basis eq.): the orthogonal
+ *     (Legendre) basis of Table 1, or its modified C0 modal basis;
  *   - tensor Gauss-Lobatto-Legendre quadrature with the Jacobian determinant
  *     (Sec. 2.1, inner-product eq.), p+2 points per direction (Sec. 5.2);
  *   - the element-wise SIPG form (Sec. 2.2, eq. IP) with the average and
@@ -58,6 +58,7 @@ typedef struct {
     const int *amap;        /* [ne][2dim][4] owner face coords -> other side's */
     const double *gll_x;    /* [OR_MAXN+1][OR_MAXN] nodes, row n holds n nodes */
     const double *gll_w;    /* same shape, weights */
+    int basis;              /* 0: Legendre (orthogonal), 1: modified C0 modal */
 } omesh;
 
 /* Legendre polynomials P_0..P_p and their derivatives at x (Bonnet's
@@ -69,6 +70,40 @@ static void legendre(int p, double x, double *P, double *dP)
     for (int i = 1; i < p; ++i) {
         P[i + 1] = ((2.0 * i + 1.0) * x * P[i] - i * P[i - 1]) / (i + 1.0);
         dP[i + 1] = (i + 1.0) * P[i] + x * dP[i];
+    }
+}
+
+/* Jacobi polynomials P^(1,1)_0..P^(1,1)_n at x and their derivatives: the
+ * three-term recurrence of the Jacobi family with alpha = beta = 1,
+ * 2k(k+2)(2k) P_k = (2k+1)(2k+2)(2k) x P_{k-1} - 2k^2(2k+2) P_{k-2}. */
+static void jacobi11(int n, double x, double *J, double *dJ)
+{
+    J[0] = 1.0; dJ[0] = 0.0;
+    if (n >= 1) { J[1] = 2.0 * x; dJ[1] = 2.0; }
+    for (int k = 2; k <= n; ++k) {
+        double a = 2.0 * k * (k + 2.0) * (2.0 * k);
+        double b = (2.0 * k + 1.0) * (2.0 * k + 2.0) * (2.0 * k);
+        double c = 2.0 * k * k * (2.0 * k + 2.0);
+        J[k] = (b * x * J[k - 1] - c * J[k - 2]) / a;
+        dJ[k] = (b * (J[k - 1] + x * dJ[k - 1]) - c * dJ[k - 2]) / a;
+    }
+}
+
+/* 1-D modes 0..p at x and their derivatives.  basis 0: Legendre P_i
+ * (Table 1, orthogonal).  basis 1: the modified C0 modal basis of Table 1
+ * (Karniadakis & Sherwin), vertex modes first: psi_0 = (1-x)/2,
+ * psi_1 = (1+x)/2, psi_i = (1-x)/2 (1+x)/2 P^(1,1)_{i-2}(x) for i >= 2. */
+static void modes_1d(int basis, int p, double x, double *P, double *dP)
+{
+    if (basis == 0) { legendre(p, x, P, dP); return; }
+    double J[OR_MAXN], dJ[OR_MAXN];
+    P[0] = 0.5 * (1.0 - x); dP[0] = -0.5;
+    if (p >= 1) { P[1] = 0.5 * (1.0 + x); dP[1] = 0.5; }
+    if (p >= 2) jacobi11(p - 2, x, J, dJ);
+    for (int i = 2; i <= p; ++i) {
+        double b = 0.25 * (1.0 - x) * (1.0 + x);
+        P[i] = b * J[i - 2];
+        dP[i] = -0.5 * x * J[i - 2] + b * dJ[i - 2];
     }
 }
 
@@ -122,13 +157,14 @@ static double invert(int d, double J[3][3], double Ji[3][3])
     return det;
 }
 
-/* All basis functions phi_i(xi) = prod_k P_{i_k}(xi_k) of order p and their
- * physical gradients grad phi_i = J^{-T} grad_xi phi_i.  Modes lexicographic,
- * first direction fastest. */
-static int basis_at(int d, int p, const double *xi, double Ji[3][3], double *phi, double *gphi)
+/* All basis functions phi_i(xi) = prod_k psi_{i_k}(xi_k) of order p (1-D
+ * modes of the given basis) and their physical gradients
+ * grad phi_i = J^{-T} grad_xi phi_i.  Modes lexicographic, first direction
+ * fastest. */
+static int basis_at(int basis, int d, int p, const double *xi, double Ji[3][3], double *phi, double *gphi)
 {
     double P[3][OR_MAXN], dP[3][OR_MAXN];
-    for (int k = 0; k < d; ++k) legendre(p, xi[k], P[k], dP[k]);
+    for (int k = 0; k < d; ++k) modes_1d(basis, p, xi[k], P[k], dP[k]);
     int np = p + 1, nm = 0;
     int n3 = (d == 3) ? np : 1;
     for (int i3 = 0; i3 < n3; ++i3)
@@ -264,7 +300,7 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
         double X[3], J[3][3], Ji[3][3];
         element_map(m, e, xi, X, J);
         double det = invert(d, J, Ji);
-        basis_at(d, p, xi, Ji, phi, gphi);
+        basis_at(m->basis, d, p, xi, Ji, phi, gphi);
         if (mode != MODE_DIAG) {
             double u, gu[3];
             field_at(d, nm, phi, gphi, xe, &u, gu);
@@ -307,7 +343,7 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
                 trace_point(m, d, nn, t, z, &wz);
                 side_geo gq;
                 side_geometry(m, nbr, fn, z, &gq);
-                basis_at(d, pn, gq.xi, gq.Ji, phn, gphn);
+                basis_at(m->basis, d, pn, gq.xi, gq.Ji, phn, gphn);
                 double un, gun[3] = {0.0, 0.0, 0.0};
                 field_at(d, nmn, phn, gphn, xn, &un, gun);
                 F[t * 4] = un;
@@ -326,7 +362,7 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
                 side_geo ge;
                 side_geometry(m, e, f, z, &ge);
                 double a = wz * ge.Js;
-                basis_at(d, p, ge.xi, ge.Ji, phi, gphi);
+                basis_at(m->basis, d, p, ge.xi, ge.Ji, phi, gphi);
                 double ue, gue[3], un, gun[3] = {0.0, 0.0, 0.0};
                 field_at(d, nm, phi, gphi, xe, &ue, gue);
                 interp_other(d, nn, gxn, F, zn, &un, gun);
@@ -356,12 +392,12 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
             } else {
                 a = wz * ge.Js;
             }
-            basis_at(d, p, ge.xi, ge.Ji, phi, gphi);
+            basis_at(m->basis, d, p, ge.xi, ge.Ji, phi, gphi);
             if (mode != MODE_DIAG) {
                 double ue, gue[3], un, gun[3];
                 field_at(d, nm, phi, gphi, xe, &ue, gue);
                 if (nbr >= 0) {
-                    basis_at(d, pn, gn.xi, gn.Ji, phn, gphn);
+                    basis_at(m->basis, d, pn, gn.xi, gn.Ji, phn, gphn);
                     field_at(d, nmn, phn, gphn, xn, &un, gun);
                 } else {               /* homogeneous mirror: u+ = -u-, grad u+ = grad u- */
                     un = -ue;
@@ -533,7 +569,7 @@ int oracle_rhs(const omesh *m, const double *s_q, const double *g_b, double *b)
                     double X[3], J[3][3], Ji[3][3];
                     element_map(m, e, xi, X, J);
                     double det = invert(d, J, Ji);
-                    basis_at(d, p, xi, Ji, phi, gphi);
+                    basis_at(m->basis, d, p, xi, Ji, phi, gphi);
                     double sv = s_q[qoff[e] + q];
                     for (int i = 0; i < nm; ++i) be[i] += w * det * phi[i] * sv;
                 }
@@ -547,7 +583,7 @@ int oracle_rhs(const omesh *m, const double *s_q, const double *g_b, double *b)
                         side_geo ge;
                         trace_point(m, d, n, t, z, &wz);
                         side_geometry(m, e, f, z, &ge);
-                        basis_at(d, p, ge.xi, ge.Ji, phi, gphi);
+                        basis_at(m->basis, d, p, ge.xi, ge.Ji, phi, gphi);
                         double a = wz * ge.Js, g = g_b[cb];
                         for (int i = 0; i < nm; ++i) {
                             double dn = 0.0;
@@ -595,7 +631,7 @@ int oracle_param_grad(const omesh *m, const double *av, const double *bv,
                     double X[3], J[3][3], Ji[3][3], ua, ub, g[3];
                     element_map(m, e, xi, X, J);
                     double det = invert(d, J, Ji);
-                    basis_at(d, p, xi, Ji, phi, gphi);
+                    basis_at(m->basis, d, p, xi, Ji, phi, gphi);
                     field_at(d, nm, phi, gphi, ae, &ua, g);
                     field_at(d, nm, phi, gphi, be, &ub, g);
                     sl += w * det * ua * ub;
@@ -618,14 +654,14 @@ int oracle_param_grad(const omesh *m, const double *av, const double *bv,
                         trace_point(m, d, nF, t, z, &wz);
                         side_geometry(m, e, f, z, &ge);
                         double a = wz * ge.Js;
-                        basis_at(d, p, ge.xi, ge.Ji, phi, gphi);
+                        basis_at(m->basis, d, p, ge.xi, ge.Ji, phi, gphi);
                         double ua, ub, una = 0.0, unb = 0.0;
                         field_at(d, nm, phi, gphi, ae, &ua, g);
                         field_at(d, nm, phi, gphi, be, &ub, g);
                         if (nbr >= 0) {
                             apply_amap(d, A, z, zn);
                             side_geometry(m, nbr, fn, zn, &gn);
-                            basis_at(d, pn, gn.xi, gn.Ji, phn, gphn);
+                            basis_at(m->basis, d, pn, gn.xi, gn.Ji, phn, gphn);
                             field_at(d, nmn, phn, gphn, av + m->dof_off[nbr], &una, g);
                             field_at(d, nmn, phn, gphn, bv + m->dof_off[nbr], &unb, g);
                             ss += tau0 * a * (ua - una) * (ub - unb);
@@ -674,7 +710,7 @@ int oracle_sample(const omesh *m, const double *x, int extra, const double *ref_
                     double X[3], J[3][3], Ji[3][3], u, g[3];
                     element_map(m, e, xi, X, J);
                     double det = invert(d, J, Ji);
-                    basis_at(d, p, xi, Ji, phi, gphi);
+                    basis_at(m->basis, d, p, xi, Ji, phi, gphi);
                     field_at(d, nm, phi, gphi, x + m->dof_off[e], &u, g);
                     long o = off[e] + q;
                     for (int a = 0; a < d; ++a) xyz[o * d + a] = X[a];
