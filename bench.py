@@ -15,9 +15,10 @@ of the same workload.  `geometry_map` repeats the application and the solves
 with deformed elements' geometric factors derived at every point from their
 trilinear maps instead of read from HBM (a variant of the method, reported
 beside the metric); `p2p` times the application with the point-to-point
-interpolation flux instead of the shared trace (the paper's alternative).
+interpolation flux instead of the shared trace (the paper's alternative);
+`modal` times it in the modified C0 modal basis of Table 1.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-map] [--no-p2p]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-map] [--no-p2p] [--no-modal]
 """
 
 from __future__ import annotations
@@ -181,6 +182,8 @@ def main():
                     help="kept for the profiling commands (the 1 GiB copy always runs)")
     ap.add_argument("--variant", default=None,
                     help="kernel structure to use instead of the autotuner's choice (profiling runs)")
+    ap.add_argument("--no-modal", action="store_true",
+                    help="skip the apply in the modified C0 modal basis")
     ap.add_argument("--no-p2p", action="store_true",
                     help="skip the apply with the point-to-point interpolation flux")
     ap.add_argument("--no-map", action="store_true",
@@ -373,6 +376,22 @@ def main():
                                                                                 L["order"]), "ms": L["ms"]}
                                    for L in lp]}
         op.flux = "shared"
+    if not args.no_modal:
+        # the modified C0 modal basis (Table 1 "Modal"): a congruent operator,
+        # run by the table-driven general kernels; reported beside the metric
+        op.basis = "modal"
+        for _ in range(args.warmup):
+            op.apply(x, out=y)
+            op.apply(x32, out=y32)
+        ms_b = time_events(lambda: op.apply(x, out=y), args.steps, stream)
+        ms_b32 = time_events(lambda: op.apply(x32, out=y32), args.steps, stream)
+        out["modal"] = {"value": ndof / (ms_b * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms_b,
+                        "fp32_value": ndof / (ms_b32 * 1e-3) / 1e9, "fp32_ms": ms_b32, "variant": op.variant}
+        op.basis = "legendre"
+        if args.variant:
+            op.variant = args.variant
+        else:
+            op.autotune(20)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, x_np)
     print(json.dumps(out))

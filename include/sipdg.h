@@ -229,6 +229,21 @@ int sipdg_get_variant(sipdg_handle h, int *variant);
  *           diagonal, parameter gradients and autotuning return EINVAL.
  *           The first switch allocates a buffer of 8 values per trace point
  *           of each interior face side (EHIP if that fails). */
+/* Modal basis of the coefficients (Table 1, quadrilateral / hexahedron):
+ *   LEGENDRE: the orthogonal basis, tensor products of Legendre P_i (default).
+ *   MODAL:    the modified C0 modal basis (Karniadakis & Sherwin), per
+ *             direction psi_0 = (1-x)/2, psi_1 = (1+x)/2 (vertex modes
+ *             first), psi_i = (1-x)/2 (1+x)/2 P^(1,1)_{i-2}(x), i >= 2.
+ * Same space, so the operator changes by a congruence with the per-element
+ * change of basis.  Switching rebuilds the 1-D tables and the Jacobi
+ * diagonal (synchronous).  The wavefront kernel structures use Legendre
+ * endpoint values in closed form, so under MODAL only the general kernels
+ * (SIPDG_VARIANT_GATHER) run; every entry point and both fluxes work. */
+#define SIPDG_BASIS_LEGENDRE 0
+#define SIPDG_BASIS_MODAL 1
+int sipdg_set_basis(sipdg_handle h, int basis);
+int sipdg_get_basis(sipdg_handle h, int *basis);
+
 #define SIPDG_FLUX_SHARED 0
 #define SIPDG_FLUX_P2P 1
 int sipdg_set_flux(sipdg_handle h, int flux);

@@ -741,6 +741,8 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         if (conc && conc[0] == '1') c->concurrent = true;
         c->fast_ok = T.dim == 3 && pmax <= 6;
         c->gfold_ok = T.dim == 3;
+        c->fast_ok0 = c->fast_ok;
+        c->gfold_ok0 = c->gfold_ok;
         c->variant = c->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
         const char *env = std::getenv("SIPDG_VARIANT");
         if (env && c->gfold_ok) {
@@ -954,6 +956,35 @@ int sipdg_set_flux(sipdg_handle h, int flux) {
 int sipdg_get_flux(sipdg_handle h, int *flux) {
     if (!h || !flux) return fail(SIPDG_EINVAL, "null argument");
     *flux = h->flux;
+    return SIPDG_OK;
+}
+
+int sipdg_set_basis(sipdg_handle h, int basis) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (basis != SIPDG_BASIS_LEGENDRE && basis != SIPDG_BASIS_MODAL) return fail(SIPDG_EINVAL, "unknown basis");
+    if (basis == h->basis) return SIPDG_OK;
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<double> tab(TAB_SIZE);
+    build_tables(tab.data(), basis);
+    HIPCHK(hipMemcpy(h->d_tab64, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice));
+    HIPCHK(launch_cast_f32(h->d_tab64, h->d_tab32, TAB_SIZE, 0));
+    h->basis = basis;
+    // the wavefront kernels evaluate Legendre endpoint values in closed form:
+    // the modal basis runs on the table-driven general kernels
+    h->fast_ok = basis == SIPDG_BASIS_LEGENDRE && h->fast_ok0;
+    h->gfold_ok = basis == SIPDG_BASIS_LEGENDRE && h->gfold_ok0;
+    h->variant = h->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
+    if (h->ne > 0) {
+        int rc = refresh_diag(h, 0);
+        if (rc) return rc;
+    }
+    HIPCHK(hipDeviceSynchronize());
+    return SIPDG_OK;
+}
+
+int sipdg_get_basis(sipdg_handle h, int *basis) {
+    if (!h || !basis) return fail(SIPDG_EINVAL, "null argument");
+    *basis = h->basis;
     return SIPDG_OK;
 }
 

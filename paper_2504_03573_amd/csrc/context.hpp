@@ -134,6 +134,8 @@ struct sipdg_ctx {
     float *d_emap32 = nullptr;
     bool geo_map = false;   // deformed elements: geometry from the map, not the stored factors
     int flux = 0;           // SIPDG_FLUX_SHARED or SIPDG_FLUX_P2P
+    int basis = 0;          // SIPDG_BASIS_LEGENDRE or SIPDG_BASIS_MODAL
+    bool fast_ok0 = false, gfold_ok0 = false;   // structures the mesh allows (Legendre basis)
     void *d_tbuf_p2p = nullptr;   // point-to-point trace buffer (FP64 units: 2 x tbuf_len)
     double *d_tau0 = nullptr;
     double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it

@@ -63,7 +63,25 @@ static void bary_weights(int n, const double *x, double *lam) {
     }
 }
 
-void build_tables(double *tab) {
+// Modified C0 modal modes (Table 1 "Modal"; Karniadakis & Sherwin), vertex
+// modes first: psi_0 = (1-x)/2, psi_1 = (1+x)/2, and for i >= 2 the bubble
+// (1-x)/2 (1+x)/2 P^(1,1)_{i-2}(x).  With P^(1,1)_{i-2} = 2 P'_{i-1} / i and
+// (1-x^2) P'_k = k(k+1)/(2k+1) (P_{k-1} - P_{k+1}) the bubble is
+// (i-1) / (2(2i-1)) (P_{i-2} - P_i): here from the Legendre values P, dP
+// (i <= p) into M, dM.
+static void legendre_to_modal(int p, const double *P, const double *dP, double *M, double *dM) {
+    M[0] = 0.5 * (P[0] - P[1]);
+    dM[0] = 0.5 * (dP[0] - dP[1]);
+    M[1] = 0.5 * (P[0] + P[1]);
+    dM[1] = 0.5 * (dP[0] + dP[1]);
+    for (int i = 2; i <= p; ++i) {
+        const double c = (i - 1.0) / (2.0 * (2.0 * i - 1.0));
+        M[i] = c * (P[i - 2] - P[i]);
+        dM[i] = c * (dP[i - 2] - dP[i]);
+    }
+}
+
+void build_tables(double *tab, int basis) {
     std::memset(tab, 0, sizeof(double) * TAB_SIZE);
     double X[NMAX + 1][NMAX], W[NMAX + 1][NMAX];
     for (int n = NMIN; n <= NMAX; ++n) {
@@ -78,6 +96,12 @@ void build_tables(double *tab) {
         int n = Pd + 2, np = Pd + 1;
         for (int q = 0; q < n; ++q) {
             legendre_with_derivs(Pd, X[n][q], P, dP);
+            if (basis == 1) {
+                double M[PMAX + 2], dM[PMAX + 2];
+                legendre_to_modal(Pd, P, dP, M, dM);
+                for (int i = 0; i < np; ++i) tab[tab_off_B(Pd) + q * np + i] = M[i];
+                continue;
+            }
             for (int i = 0; i < np; ++i) tab[tab_off_B(Pd) + q * np + i] = P[i];
         }
     }
@@ -115,6 +139,14 @@ void build_tables(double *tab) {
     for (int m = NMIN; m <= NMAX; ++m) {
         for (int t = 0; t < m; ++t) {
             legendre_with_derivs(PMAX, X[m][t], P, dP);
+            if (basis == 1) {
+                double M[PMAX + 2], dM[PMAX + 2];
+                legendre_to_modal(PMAX, P, dP, M, dM);
+                for (int i = 0; i <= PMAX; ++i) {
+                    P[i] = M[i];
+                    dP[i] = dM[i];
+                }
+            }
             for (int i = 0; i <= PMAX; ++i) {
                 tab[tab_off_BF(m) + t * (PMAX + 1) + i] = P[i];
                 tab[tab_off_DBF(m) + t * (PMAX + 1) + i] = dP[i];

@@ -3,12 +3,13 @@
 // All sum-factorised operators of the library are built from these 1-D
 // matrices (Xia & Moxey, Sec. 3.1 basic operators; Sec. 3.2 trace
 // evaluation):
-//   B(P)    [n][N_P]  Legendre P_i at the n = P+2 GLL points (BwdTrans rows,
-//                     the transpose gives IProduct)
+//   B(P)    [n][N_P]  modes at the n = P+2 GLL points (BwdTrans rows, the
+//                     transpose gives IProduct): Legendre P_i, or the modified
+//                     C0 modes (Table 1 "Modal")
 //   D(n)    [n][n]    collocation derivative l'_j(x_i) (PhysDeriv)
 //   I(n,m)  [m][n]    Lagrange interpolation from n to m > n GLL points
 //                     (gather + interpolate to the shared trace)
-//   BF(m)   [m][PMAX+1], DBF(m): P_i and P'_i at m GLL points
+//   BF(m)   [m][PMAX+1], DBF(m): modes and their derivatives at m GLL points
 //   X(n), W(n)        GLL nodes and weights
 #pragma once
 
@@ -43,8 +44,9 @@ constexpr int tab_off_X(int n) { return TAB_DBF_END + (n - NMIN) * NMAX; }
 constexpr int tab_off_W(int n) { return TAB_DBF_END + NPAIR * NMAX + (n - NMIN) * NMAX; }
 constexpr int TAB_SIZE = TAB_DBF_END + 2 * NPAIR * NMAX;
 
-// Host: fill a TAB_SIZE array (FP64).
-void build_tables(double *tab);
+// Host: fill a TAB_SIZE array (FP64) for the given modal basis (0 Legendre,
+// 1 modified C0; B, BF and DBF depend on it, the rest does not).
+void build_tables(double *tab, int basis = 0);
 
 // Host helpers also used by the topology/validation code.
 void gll_nodes_weights(int n, double *x, double *w);

@@ -197,6 +197,18 @@ class SipdgOperator:
         C.check(self._lib.sipdg_set_geometry(self._h, C.GEOMETRY[name]))
 
     @property
+    def basis(self) -> str:
+        """Modal basis of the coefficients: "legendre" (orthogonal, the
+        default) or "modal" (modified C0; runs on the general kernels)."""
+        v = ctypes.c_int()
+        C.check(self._lib.sipdg_get_basis(self._h, ctypes.byref(v)))
+        return {b: a for a, b in C.BASIS.items()}[v.value]
+
+    @basis.setter
+    def basis(self, name: str):
+        C.check(self._lib.sipdg_set_basis(self._h, C.BASIS[name]))
+
+    @property
     def flux(self) -> str:
         """Interior-face flux of apply: "shared" (shared trace space, the
         default) or "p2p" (point-to-point interpolation; nonsymmetric, only
