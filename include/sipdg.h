@@ -236,9 +236,10 @@ int sipdg_get_variant(sipdg_handle h, int *variant);
  *             first), psi_i = (1-x)/2 (1+x)/2 P^(1,1)_{i-2}(x), i >= 2.
  * Same space, so the operator changes by a congruence with the per-element
  * change of basis.  Switching rebuilds the 1-D tables and the Jacobi
- * diagonal (synchronous).  The wavefront kernel structures use Legendre
- * endpoint values in closed form, so under MODAL only the general kernels
- * (SIPDG_VARIANT_GATHER) run; every entry point and both fluxes work. */
+ * diagonal (synchronous).  GATHER and GATHER_FOLD (the default) take either
+ * basis; TWO_STAGE, FUSED, GATHER_FOLD_FUSED and GATHER_FOLD_PERSISTENT use
+ * Legendre endpoint values in closed form and return EINVAL under MODAL.
+ * Every entry point and both fluxes work. */
 #define SIPDG_BASIS_LEGENDRE 0
 #define SIPDG_BASIS_MODAL 1
 int sipdg_set_basis(sipdg_handle h, int basis);

@@ -186,7 +186,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 f3::Data3<R> D3;
                 fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
-                           A3.skip, c->d_pdesc, c->d_pfdesc};
+                           A3.skip, c->d_pdesc, c->d_pfdesc, c->basis};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                 rec_mark(rec, stage, -1, false, st);
                 hipError_t e = launch_gfold3d_persistent<R>(stage == 1 ? 0 : 1, c->num_cu * c->blocks_per_cu, A, D, st);
@@ -205,7 +205,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                     f3::Data3<R> D3;
                     fast_args<R>(c, g, x, y, tbuf, skip, false, A3, D3);
                     g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
-                               A3.toff, A3.skip, g.d_desc, g.d_fdesc};
+                               A3.toff, A3.skip, g.d_desc, g.d_fdesc, c->basis};
                     g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                     e = launch_gfold3d<R>(g.P, stage == 1 ? 0 : 1, g.nfmax, A, D, st);
                 } else {
@@ -238,7 +238,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 f3::Data3<R> D3;
                 fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
-                           A3.skip, c->d_pdesc, c->d_pfdesc};
+                           A3.skip, c->d_pdesc, c->d_pfdesc, c->basis};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                 rec_mark(rec, stage, -1, false, main_st);
                 hipError_t e = launch_gfold3d_trace_all<R>(A, D, main_st);
@@ -277,7 +277,7 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 f3::Data3<R> D3;
                 fast_args<R>(c, g, x, y, tbuf, skip, fused, A3, D3);
                 g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
-                           A3.skip, g.d_desc, g.d_fdesc};
+                           A3.skip, g.d_desc, g.d_fdesc, c->basis};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
                 rec_mark(rec, stage, (int)gi, false, st);
                 hipError_t e = hipSuccess;
@@ -969,10 +969,10 @@ int sipdg_set_basis(sipdg_handle h, int basis) {
     HIPCHK(hipMemcpy(h->d_tab64, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice));
     HIPCHK(launch_cast_f32(h->d_tab64, h->d_tab32, TAB_SIZE, 0));
     h->basis = basis;
-    // the wavefront kernels evaluate Legendre endpoint values in closed form:
-    // the modal basis runs on the table-driven general kernels
+    // the two-stage, fused and persistent structures evaluate Legendre
+    // endpoint values in closed form; gather and gather-fold take either basis
     h->fast_ok = basis == SIPDG_BASIS_LEGENDRE && h->fast_ok0;
-    h->gfold_ok = basis == SIPDG_BASIS_LEGENDRE && h->gfold_ok0;
+    h->gfold_ok = h->gfold_ok0;
     h->variant = h->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
     if (h->ne > 0) {
         int rc = refresh_diag(h, 0);
@@ -1115,6 +1115,8 @@ int sipdg_set_variant(sipdg_handle h, int variant) {
         return fail(SIPDG_EINVAL, "unknown variant");
     if (variant == SIPDG_VARIANT_GATHER_FOLD || variant == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT) {
         if (!h->gfold_ok) return fail(SIPDG_EINVAL, "gather_fold needs a 3-D mesh");
+        if (variant == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT && h->basis != SIPDG_BASIS_LEGENDRE)
+            return fail(SIPDG_EINVAL, "the persistent structure needs the Legendre basis");
     } else if (!h->fast_ok) {
         return fail(SIPDG_EINVAL, "variant needs a 3-D mesh with every order <= 6");
     }
@@ -1163,6 +1165,7 @@ int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
         if (ms_out) ms_out[v] = 0.0;
         const bool gf = v == SIPDG_VARIANT_GATHER_FOLD || v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT;
         if (gf ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)) continue;
+        if (v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT && h->basis != SIPDG_BASIS_LEGENDRE) continue;
         h->variant = v;
         // the persistent launch also tunes its shape: blocks per compute unit
         const int shapes[] = {2, 4, 6, 8, 12, 16};

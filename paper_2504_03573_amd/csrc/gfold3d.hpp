@@ -103,6 +103,7 @@ struct Args {
     const int *skip;
     const ElemDesc *desc;    // [count]
     const FaceDesc *fdesc;   // [count][6]
+    int basis = 0;           // host side: 0 Legendre, 1 modified C0 modal (trace kernels)
 };
 
 template <class R>
@@ -1221,7 +1222,7 @@ struct TSz {
     static constexpr int TOTAL = XS + NU + NW + BT;
 };
 
-template <class R, int P>
+template <class R, int P, int BASIS = 0>
 __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
     using T = TSz<P>;
     constexpr int NP = T::NP, N = T::N, WG = T::W, SG = Geo<P>::S, NM = NP * NP * NP;
@@ -1297,12 +1298,32 @@ __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int bl
             for (int ik = 0; ik < NP; ++ik) {
                 const int idx = k == 0 ? ik + NP * (a + NP * b) : (k == 1 ? a + NP * (ik + NP * b) : a + NP * (b + NP * ik));
                 const R xv = XS[idx];
-                const R dv = R(0.5 * ik * (ik + 1));
-                const R sx = (ik & 1) ? -xv : xv;
-                r0 += sx;
-                r1 -= dv * sx;
-                r2 += xv;
-                r3 += dv * xv;
+                if constexpr (BASIS == 0) {
+                    // Legendre: P_i(+-1) = (+-1)^i, P'_i(+-1) = (+-1)^(i+1) i(i+1)/2
+                    const R dv = R(0.5 * ik * (ik + 1));
+                    const R sx = (ik & 1) ? -xv : xv;
+                    r0 += sx;
+                    r1 -= dv * sx;
+                    r2 += xv;
+                    r3 += dv * xv;
+                } else {
+                    // modified C0: psi_0(-1) = psi_1(+1) = 1, bubbles vanish at
+                    // the ends; psi'_0 = -1/2, psi'_1 = 1/2, and for i >= 2
+                    // psi'_i(-1) = (-1)^i (i-1)/2, psi'_i(+1) = -(i-1)/2
+                    if (ik == 0) {
+                        r0 += xv;
+                        r1 -= R(0.5) * xv;
+                        r3 -= R(0.5) * xv;
+                    } else if (ik == 1) {
+                        r2 += xv;
+                        r1 += R(0.5) * xv;
+                        r3 += R(0.5) * xv;
+                    } else {
+                        const R dv = R(0.5 * (ik - 1));
+                        r1 += (ik & 1) ? -dv * xv : dv * xv;
+                        r3 -= dv * xv;
+                    }
+                }
             }
         }
         NU[l] = r0;
@@ -1356,27 +1377,27 @@ __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int bl
     }
 }
 
-template <class R, int P>
+template <class R, int P, int BASIS = 0>
 __global__ __launch_bounds__(Geo<P>::W) void k3t(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    k3t_elem<R, P>(A, D, blockIdx.x, smem_raw);
+    k3t_elem<R, P, BASIS>(A, D, blockIdx.x, smem_raw);
 }
 
 // Trace stage of every element of order <= 6 (traces <= 8 x 8) in one launch:
 // block b takes element b of A.desc / A.fdesc, its order in ElemDesc::pad.
-template <class R>
+template <class R, int BASIS = 0>
 __global__ __launch_bounds__(W) void k3t_all(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;
     switch (A.desc[i].pad & ELEM_ORDER_MASK) {
-    case 1: k3t_elem<R, 1>(A, D, i, smem_raw); break;
-    case 2: k3t_elem<R, 2>(A, D, i, smem_raw); break;
-    case 3: k3t_elem<R, 3>(A, D, i, smem_raw); break;
-    case 4: k3t_elem<R, 4>(A, D, i, smem_raw); break;
-    case 5: k3t_elem<R, 5>(A, D, i, smem_raw); break;
-    default: k3t_elem<R, 6>(A, D, i, smem_raw); break;
+    case 1: k3t_elem<R, 1, BASIS>(A, D, i, smem_raw); break;
+    case 2: k3t_elem<R, 2, BASIS>(A, D, i, smem_raw); break;
+    case 3: k3t_elem<R, 3, BASIS>(A, D, i, smem_raw); break;
+    case 4: k3t_elem<R, 4, BASIS>(A, D, i, smem_raw); break;
+    case 5: k3t_elem<R, 5, BASIS>(A, D, i, smem_raw); break;
+    default: k3t_elem<R, 6, BASIS>(A, D, i, smem_raw); break;
     }
 }
 __host__ __device__ constexpr int lds_trace_all() {
