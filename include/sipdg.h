@@ -343,6 +343,36 @@ typedef struct {
 
 void sipdg_cg_default_opts(sipdg_cg_opts *o);
 
+/* Restarted GMRES(restart) for A x = b with the handle's current operator,
+ * either interface flux: the point-to-point flux makes A nonsymmetric, and
+ * the paper solves those systems with GMRES (Table 2).  FP64 throughout.
+ * Right preconditioning with the Jacobi diagonal of the shared-trace
+ * operator (precond = 1; an approximation of the point-to-point diagonal),
+ * Arnoldi by classical Gram-Schmidt applied twice, Givens rotations.  x
+ * starts from zero; stop when ||b - A x||_2 <= tol ||b||_2 (the true residual
+ * at a restart; inside a cycle the Arnoldi estimate).  maxit bounds the
+ * Arnoldi steps.  A batched handle is solved as one system (tol applies to
+ * the whole vector).  Device memory: (restart + 3) vectors for the call.
+ * Synchronous.  Errors: EINVAL, ENOCONV (info filled), EHIP. */
+typedef struct {
+    double tol;       /* 1e-10 */
+    int restart;      /* Krylov vectors per cycle, 1..1000 (30) */
+    int maxit;        /* max Arnoldi steps in total (100000) */
+    int precond;      /* 1 = Jacobi (shared-trace diagonal), 0 = none */
+} sipdg_gmres_opts;
+
+typedef struct {
+    int iters;          /* Arnoldi steps */
+    int restarts;       /* completed cycles */
+    int converged;
+    double rel_resid;   /* true ||b - A x|| / ||b|| at the end */
+    double time_ms;
+} sipdg_gmres_info;
+
+void sipdg_gmres_default_opts(sipdg_gmres_opts *o);
+int sipdg_gmres_solve(sipdg_handle h, const double *b, double *x, const sipdg_gmres_opts *opts,
+                      sipdg_gmres_info *info, void *stream);
+
 /* Solve A x = b (device FP64 vectors).  Synchronous: returns when done.
  * Errors: ENOCONV, EBREAKDOWN, EINVAL, EHIP. */
 int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_opts *opts,

@@ -95,6 +95,25 @@ class CgInfo(ctypes.Structure):
     ]
 
 
+class GmresOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("restart", ctypes.c_int),
+        ("maxit", ctypes.c_int),
+        ("precond", ctypes.c_int),
+    ]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("rel_resid", ctypes.c_double),
+        ("time_ms", ctypes.c_double),
+    ]
+
+
 class LaunchInfo(ctypes.Structure):
     _fields_ = [
         ("ms", ctypes.c_double),
@@ -131,6 +150,8 @@ SIGNATURES = {
     "sipdg_load_vector": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "sipdg_cg_default_opts": (None, [ctypes.POINTER(CgOpts)]),
     "sipdg_cg_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(CgOpts), ctypes.POINTER(CgInfo), _vp]),
+    "sipdg_gmres_default_opts": (None, [ctypes.POINTER(GmresOpts)]),
+    "sipdg_gmres_solve": (_i, [_vp, _vp, _vp, ctypes.POINTER(GmresOpts), ctypes.POINTER(GmresInfo), _vp]),
     "sipdg_set_variant": (_i, [_vp, _i]),
     "sipdg_get_variant": (_i, [_vp, ctypes.POINTER(_i)]),
     "sipdg_set_geometry": (_i, [_vp, _i]),

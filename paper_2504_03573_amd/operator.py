@@ -270,6 +270,24 @@ class SipdgOperator:
         g = dirichlet(xb).contiguous() if self.n_boundary_points else torch.zeros(1, dtype=torch.float64, device=self.device)
         return self.load_vector(s, g)
 
+    def gmres_solve(self, b: torch.Tensor, tol: float = 1e-10, restart: int = 30, maxit: int = 100000,
+                    precond: bool = True, raise_on_fail: bool = True, stream=None):
+        """Restarted GMRES for A x = b (FP64, x from zero) with the current
+        interface flux; the point-to-point flux needs it (nonsymmetric A)."""
+        self._vec(b, torch.float64, name="b")
+        x = torch.empty_like(b)
+        o = C.GmresOpts()
+        self._lib.sipdg_gmres_default_opts(ctypes.byref(o))
+        o.tol, o.restart, o.maxit, o.precond = float(tol), int(restart), int(maxit), int(bool(precond))
+        info = C.GmresInfo()
+        rc = self._lib.sipdg_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
+                                         _stream_ptr(stream))
+        out = {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
+               "rel_resid": info.rel_resid, "time_ms": info.time_ms}
+        if rc != 0 and not (rc == -5 and not raise_on_fail):
+            C.check(rc)
+        return x, out
+
     def cg_solve(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
                  maxit: int = 20000, mode: str = "f64", inner_tol: float = 1e-4, ru_delta: float = 0.1,
                  precond: bool = True, graph_k: int = 10, max_outer: int = 50,
