@@ -223,12 +223,14 @@ int sipdg_get_variant(sipdg_handle h, int *variant);
  *           integrates on its own p + 2 GLL face points with the other
  *           side's value and physical gradient Lagrange-interpolated to them.
  *           Not symmetric in general (Sec. 3.3 conditions, Table 2).  3-D.
- *           While set, only sipdg_apply, sipdg_apply_stage and
- *           sipdg_apply_timed are allowed (default kernel structure ignored:
- *           one trace and one apply launch per order group); CG, transpose,
- *           diagonal, parameter gradients and autotuning return EINVAL.
+ *           While set, sipdg_apply, sipdg_apply_stage, sipdg_apply_timed
+ *           (default kernel structure ignored: one trace and one apply
+ *           launch per order group) and sipdg_gmres_solve use it; CG,
+ *           transpose, diagonal, parameter gradients and autotuning return
+ *           EINVAL.
  *           The first switch allocates a buffer of 8 values per trace point
  *           of each interior face side (EHIP if that fails). */
+
 /* Modal basis of the coefficients (Table 1, quadrilateral / hexahedron):
  *   LEGENDRE: the orthogonal basis, tensor products of Legendre P_i (default).
  *   MODAL:    the modified C0 modal basis (Karniadakis & Sherwin), per

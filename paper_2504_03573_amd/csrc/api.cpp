@@ -933,8 +933,8 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
 }
 
 static const char *P2P_ONLY_APPLY =
-    "the point-to-point flux gives a nonsymmetric operator: only sipdg_apply, sipdg_apply_stage and "
-    "sipdg_apply_timed use it (set SIPDG_FLUX_SHARED for this call)";
+    "the point-to-point flux gives a nonsymmetric operator: only the apply calls and GMRES use it "
+    "(set SIPDG_FLUX_SHARED for this call)";
 
 int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision, void *stream) {
     if (h && h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
