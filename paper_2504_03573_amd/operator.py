@@ -211,8 +211,8 @@ class SipdgOperator:
     @property
     def flux(self) -> str:
         """Interior-face flux of apply: "shared" (shared trace space, the
-        default) or "p2p" (point-to-point interpolation; nonsymmetric, only
-        apply / apply_stage / apply_timed accept it)."""
+        default) or "p2p" (point-to-point interpolation; nonsymmetric: the
+        apply calls and gmres_solve accept it)."""
         v = ctypes.c_int()
         C.check(self._lib.sipdg_get_flux(self._h, ctypes.byref(v)))
         return {b: a for a, b in C.FLUX.items()}[v.value]
