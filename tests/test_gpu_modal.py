@@ -114,8 +114,18 @@ def test_switch_back_to_legendre(P, orc):
     x = torch.tensor(synth.random_coefficients(m, 7104), device="cuda")
     y0 = op.apply(x)
     d0 = op.diagonal()
+    # captured CG iterations before and after a switch: the graphs are
+    # captured again for the other basis (same kernel structure)
+    xs0, _ = op.cg_solve(y0, tol=1e-10, graph_k=5)
     op.basis = "modal"
+    om = orc.prepare(m, "modal")
+    b = om.apply(synth.random_coefficients(m, 7105))
+    xs1, info = op.cg_solve(torch.tensor(b, device="cuda"), tol=1e-10, graph_k=5)
+    assert info["converged"]
+    assert np.linalg.norm(b - om.apply(xs1.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
     op.basis = "legendre"
     assert op.variant == default
     assert torch.equal(op.apply(x), y0)
     assert torch.equal(op.diagonal(), d0)
+    xs2, _ = op.cg_solve(y0, tol=1e-10, graph_k=5)
+    assert torch.equal(xs2, xs0)
