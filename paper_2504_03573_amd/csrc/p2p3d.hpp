@@ -53,29 +53,28 @@ __device__ __forceinline__ R map_adjugate(const R *cm, R x0, R x1, R x2, R r[3][
     return j0[0] * r[0][0] + j0[1] * r[0][1] + j0[2] * r[0][2];
 }
 
-// One face point of the element of block slot el: local face f = 2k + s,
-// own face coordinates (a, b).  Loads u and grad_xi u from the element's
-// fields in LDS and returns the point's geometry.
-template <class R, int P>
+// Value, physical gradient and geometry at one face point.
+template <class R>
 struct P2PPoint {
     R u, gx[3];     // value and physical gradient
     R r[3][3], det; // rows of adj(J), det J
-    int q;          // element point index
 };
 
+// Face point (a, b) (own face coordinates) of local face f = 2k + s of
+// element e, whose fields u and grad_xi u are in LDS at sm.
 template <class R, int P>
-__device__ __forceinline__ P2PPoint<R, P> p2p_point(const OpArgs<R> &A, const R *sm, int es, int e, int k, int s,
-                                                   int a, int b) {
+__device__ __forceinline__ P2PPoint<R> p2p_point(const OpArgs<R> &A, const R *sm, int e, int k, int s, int a,
+                                                 int b) {
     using C = Cfg<3, P>;
     using Ly = Lay<3, P>;
     constexpr int N = C::N;
-    P2PPoint<R, P> pt;
-    pt.q = face_point<3, N>(k, s, a, b);
-    const int i0 = pt.q % N, i1 = (pt.q / N) % N, i2 = pt.q / (N * N);
+    P2PPoint<R> pt;
+    const int q = face_point<3, N>(k, s, a, b);
+    const int i0 = q % N, i1 = (q / N) % N, i2 = q / (N * N);
     const R *X = A.tab + tab_off_X(N);
     pt.det = map_adjugate<R>(A.emap + (int64_t)24 * e, X[i0], X[i1], X[i2], pt.r);
-    pt.u = sm[Ly::U + pt.q];
-    const R d0 = sm[Ly::G + pt.q], d1 = sm[Ly::G + C::NPTS + pt.q], d2 = sm[Ly::G + 2 * C::NPTS + pt.q];
+    pt.u = sm[Ly::U + q];
+    const R d0 = sm[Ly::G + q], d1 = sm[Ly::G + C::NPTS + q], d2 = sm[Ly::G + 2 * C::NPTS + q];
     const R inv = R(1) / pt.det;
 #pragma unroll
     for (int c = 0; c < 3; ++c) pt.gx[c] = (pt.r[0][c] * d0 + pt.r[1][c] * d1 + pt.r[2][c] * d2) * inv;
@@ -106,7 +105,7 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_trace(OpArgs<R> A) {
         const int slot = face_slot(fr.info);
         if (slot == 2) continue;
         const int a = fp % N, b = fp / N;
-        const P2PPoint<R, P> pt = p2p_point<R, P>(A, sm + el * es, es, s_e[el], f / 2, f & 1, a, b);
+        const P2PPoint<R> pt = p2p_point<R, P>(A, sm + el * es, s_e[el], f / 2, f & 1, a, b);
         const int nf = face_nf(fr.info), npf = nf * nf;
         const int qc = canon_index(face_orient(fr.info), N, a, b);
         R *tb = A.tbuf + 2 * A.toff[fr.F] + (int64_t)slot * 4 * npf;
@@ -202,7 +201,7 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A, int nfm) {
             const FaceRef fr = s_face[el * 6 + f];
             const int slot = face_slot(fr.info);
             const int a = fp % N, b = fp / N;
-            const P2PPoint<R, P> pt = p2p_point<R, P>(A, sm + el * es, es, s_e[el], k, s, a, b);
+            const P2PPoint<R> pt = p2p_point<R, P>(A, sm + el * es, s_e[el], k, s, a, b);
             // area-weighted outward normal times the quadrature weight: w s adj row k
             const R w = W[a] * W[b];
             R an[3];
