@@ -106,6 +106,15 @@ def kernel_name(variant, order, stage=2, geo_map=False):
     return "sipdg::k_%s<double, 3, %d>" % ("trace" if stage == 1 else "apply", order)
 
 
+def p2p_kernel_name(variant, order, stage):
+    """Kernel symbol of a launch of the point-to-point application."""
+    if variant == "gather":
+        return "sipdg::k_p2p_%s<double, %d>" % ("trace" if stage == 1 else "apply", order)
+    if stage == 1:
+        return "sipdg::k_p2p_trace_gf<double, %d>" % order
+    return "sipdg::g3::k3g<double, %d, 1, 0>" % order
+
+
 def time_events(fn, n, stream):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -372,8 +381,8 @@ def main():
         lp = op.apply_timed(x, y, reps=max(10, min(args.steps, 100)), stream=stream)
         out["p2p"] = {"value": ndof / (ms_p * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms_p,
                       "fp32_value": ndof / (ms_p32 * 1e-3) / 1e9, "fp32_ms": ms_p32,
-                      "launches": [{"kernel": "sipdg::k_p2p_%s<double, %d>" % ("trace" if L["stage"] == 1 else "apply",
-                                                                                L["order"]), "ms": L["ms"]}
+                      "variant": op.variant,
+                      "launches": [{"kernel": p2p_kernel_name(op.variant, L["order"], L["stage"]), "ms": L["ms"]}
                                    for L in lp]}
         op.flux = "shared"
     if not args.no_modal:

@@ -159,9 +159,52 @@ static const R *emap_of(const sipdg_ctx *c) {
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
                LaunchRec *rec) {
+    if (c->flux == SIPDG_FLUX_P2P && c->variant != SIPDG_VARIANT_GATHER) {
+        // point-to-point flux through the gather-fold apply: per order group a
+        // trace launch (own pair, and the trace interpolated to each
+        // neighbour's points), then the apply with every face side on its own
+        // point set (nf = n: no lift)
+        R *pb = (R *)c->d_tbuf_p2p;
+        const R *fgp = sizeof(R) == 8 ? (const R *)c->d_fgeo_p2p64 : (const R *)c->d_fgeo_p2p32;
+        for (int stage = 1; stage <= 2; ++stage) {
+            if (!(stages & stage)) continue;
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
+                rec_mark(rec, stage, (int)gi, false, st);
+                hipError_t e = hipSuccess;
+                if (stage == 1) {
+                    OpArgs<R> A = make_args<R>(c, g, x, y, pb, skip);
+                    e = launch_p2p_trace_gf<R>(g.P, A, g.nfmax, c->d_p2p_side, fgp, st);
+                } else {
+                    f3::Args3 A3;
+                    f3::Data3<R> D3;
+                    fast_args<R>(c, g, x, y, pb, skip, false, A3, D3);
+                    g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
+                               A3.toff, A3.skip, g.d_desc, g.d_fdesc_p2p, c->basis};
+                    g3::Data<R> D{D3.vgeo, fgp, D3.lam, D3.tau, D3.tab, D3.x, D3.y, pb, egeo_of<R>(c), emap_of<R>(c)};
+                    const int mode = c->geo_map ? 4 : 1;
+                    if (g.split) {
+                        g3::Args Aa = A, Ad = A;
+                        Aa.count = g.naff;
+                        Ad.count = g.count - g.naff;
+                        Ad.desc = g.d_desc + g.naff;
+                        Ad.fdesc = g.d_fdesc_p2p + (int64_t)6 * g.naff;
+                        e = launch_gfold3d<R>(g.P, 3, g.P + 2, Aa, D, st);
+                        if (e == hipSuccess) e = launch_gfold3d<R>(g.P, mode, g.P + 2, Ad, D, st);
+                    } else {
+                        e = launch_gfold3d<R>(g.P, mode, g.P + 2, A, D, st);
+                    }
+                }
+                rec_mark(rec, stage, (int)gi, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string("point-to-point kernel: ") + hipGetErrorString(e));
+            }
+        }
+        return SIPDG_OK;
+    }
     if (c->flux == SIPDG_FLUX_P2P) {
-        // point-to-point flux: per order group, a trace launch (own face
-        // points) then an apply launch, on the handle's own buffer
+        // point-to-point flux, general kernels (the gather structure): per
+        // order group, a trace launch (own face points) then an apply launch
         R *pb = (R *)c->d_tbuf_p2p;
         for (int stage = 1; stage <= 2; ++stage) {
             if (!(stages & stage)) continue;
@@ -408,7 +451,7 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
                     c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32,
-                    c->d_tbuf_p2p};
+                    c->d_tbuf_p2p, c->d_p2p_side, c->d_fgeo_p2p64, c->d_fgeo_p2p32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->d_pdesc) (void)hipFree(c->d_pdesc);
@@ -424,6 +467,7 @@ static void free_ctx(sipdg_ctx *c) {
         if (g.d_elems) (void)hipFree(g.d_elems);
         if (g.d_desc) (void)hipFree(g.d_desc);
         if (g.d_fdesc) (void)hipFree(g.d_fdesc);
+        if (g.d_fdesc_p2p) (void)hipFree(g.d_fdesc_p2p);
     }
     free_cg(c);
     delete c;
@@ -941,13 +985,69 @@ int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precisi
     return sipdg_apply(h, g, xbar, precision, stream);
 }
 
+// Point-to-point flux structures (first switch): the buffer, and for the
+// gather-fold apply each face side's own point set: offsets, factors from the
+// element maps, and per order group the face descriptors in launch order.
+static int build_p2p(sipdg_ctx *h) {
+    const int64_t nf = h->nfaces, ne = h->ne;
+    std::vector<FaceTopo> faces(std::max<int64_t>(nf, 1));
+    std::vector<int> order(std::max<int64_t>(ne, 1));
+    std::vector<FaceRef> eface(std::max<int64_t>(ne * 6, 1));
+    if (nf > 0) HIPCHK(hipMemcpy(faces.data(), h->d_faces, sizeof(FaceTopo) * nf, hipMemcpyDeviceToHost));
+    if (ne > 0) {
+        HIPCHK(hipMemcpy(order.data(), h->d_order, sizeof(int) * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(eface.data(), h->d_eface, sizeof(FaceRef) * ne * 6, hipMemcpyDeviceToHost));
+    }
+    std::vector<int64_t> side((size_t)std::max<int64_t>(nf, 1) * 4, 0);
+    int64_t fo = 0, to = 0;
+    for (int64_t F = 0; F < nf; ++F) {
+        const FaceTopo &ft = faces[F];
+        for (int s = 0; s < (ft.eR >= 0 ? 2 : 1); ++s) {
+            const int n = order[s ? ft.eR : ft.eL] + 2;
+            side[F * 4 + 2 * s] = fo;
+            side[F * 4 + 2 * s + 1] = to;
+            fo += 7 * (int64_t)n * n;
+            to += (ft.eR >= 0 ? 4 : 2) * (int64_t)n * n;
+        }
+    }
+    // one buffer for both p2p structures: the general kernels use 2 x toff
+    HIPCHK(hipMalloc(&h->d_tbuf_p2p, sizeof(double) * std::max<int64_t>(1, std::max(2 * h->tbuf_len, to))));
+    int rc = upload(&h->d_p2p_side, side);
+    if (!rc) rc = dalloc(&h->d_fgeo_p2p64, std::max<int64_t>(fo, 1));
+    if (!rc) rc = dalloc(&h->d_fgeo_p2p32, std::max<int64_t>(fo, 1));
+    if (rc) return rc;
+    HIPCHK(launch_p2p_factors(nf, h->d_faces, h->d_order, h->d_p2p_side, h->d_emap64, h->d_tab64, h->d_fgeo_p2p64, 0));
+    HIPCHK(launch_cast_f32(h->d_fgeo_p2p64, h->d_fgeo_p2p32, std::max<int64_t>(fo, 1), 0));
+    for (Group &g : h->groups) {
+        std::vector<ElemDesc> desc(g.count);
+        HIPCHK(hipMemcpy(desc.data(), g.d_desc, sizeof(ElemDesc) * g.count, hipMemcpyDeviceToHost));
+        std::vector<FaceDesc> fd((size_t)g.count * 6);
+        for (int i = 0; i < g.count; ++i) {
+            const int e = desc[i].e, n = order[e] + 2;
+            for (int f = 0; f < 6; ++f) {
+                const FaceRef fr = eface[(size_t)e * 6 + f];
+                const int slot = face_slot(fr.info), si = slot == 1 ? 1 : 0;
+                const int info = slot | (face_orient(fr.info) << 2) | (n << 5);
+                fd[(size_t)i * 6 + f] = FaceDesc{side[(size_t)fr.F * 4 + 2 * si], side[(size_t)fr.F * 4 + 2 * si + 1],
+                                                 fr.F, info};
+            }
+        }
+        rc = upload(&g.d_fdesc_p2p, fd);
+        if (rc) return rc;
+    }
+    HIPCHK(hipDeviceSynchronize());
+    return SIPDG_OK;
+}
+
 int sipdg_set_flux(sipdg_handle h, int flux) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (flux != SIPDG_FLUX_SHARED && flux != SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, "unknown flux");
     if (flux == SIPDG_FLUX_P2P) {
         if (h->dim != 3) return fail(SIPDG_EINVAL, "the point-to-point flux needs a 3-D mesh");
-        if (!h->d_tbuf_p2p)
-            HIPCHK(hipMalloc(&h->d_tbuf_p2p, sizeof(double) * std::max<int64_t>(1, 2 * h->tbuf_len)));
+        if (!h->d_tbuf_p2p) {
+            int rc = build_p2p(h);
+            if (rc) return rc;
+        }
     }
     h->flux = flux;
     return SIPDG_OK;

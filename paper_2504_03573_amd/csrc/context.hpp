@@ -83,6 +83,7 @@ struct Group {
     int naff = 0;                    // affine elements of the group (3-D)
     bool split = false;              // apply: affine part and deformed part launched apart
     FaceDesc *d_fdesc = nullptr;     // [count][6]   (3-D)
+    FaceDesc *d_fdesc_p2p = nullptr; // [count][6]   point-to-point flux: own point sets
     double alg_bytes[2] = {0, 0};    // algorithmic bytes of the group's elements (FP64, FP32)
 };
 
@@ -137,6 +138,9 @@ struct sipdg_ctx {
     int basis = 0;          // SIPDG_BASIS_LEGENDRE or SIPDG_BASIS_MODAL
     bool fast_ok0 = false, gfold_ok0 = false;   // structures the mesh allows (Legendre basis)
     void *d_tbuf_p2p = nullptr;   // point-to-point trace buffer (FP64 units: 2 x tbuf_len)
+    int64_t *d_p2p_side = nullptr;           // [nf][2][factor offset, buffer offset] (gather-fold p2p)
+    double *d_fgeo_p2p64 = nullptr;          // per face side: a, C, an on its own grid
+    float *d_fgeo_p2p32 = nullptr;
     double *d_tau0 = nullptr;
     double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it
     double *d_tbuf2 = nullptr;             // second trace buffer (gradients), lazy

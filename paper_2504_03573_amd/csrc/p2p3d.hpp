@@ -239,4 +239,159 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A, int nfm) {
     element_iproduct<R, 3, P>(A.y, A.xoff, Bt, Dt, sm, es, s_e, nel);
 }
 
+// ---------------------------------------------------------------------------
+// Point-to-point flux through the gather-fold apply (k3g, unchanged): each
+// face side gets its own point set (nf = its own n) with
+//   factors  (canonical order on its own n x n grid, w the own GLL weights):
+//            a = w J_s, C_m = w J_s n . J^-T e_m, and an = w J_s n (vector),
+//            laid out [a | C | an] on the owner side and [a | an | C] on the
+//            other side (the apply reads C at 1 or 4 npf by slot);
+//   buffer   own (u, g = an . grad u) and the neighbour's (u, -an . I grad u_o),
+//            both on this side's grid, at the slots the apply reads.
+// The trace kernel below writes both: its own pair, and its trace
+// interpolated to the neighbour's points for the neighbour (Sec. 3.3,
+// ScatrInterp), using the neighbour's an.
+
+// Factors of every face side (one block per side, FP64); boundary faces have
+// one side (slot 0 layout).  side[F * 4 + 2 s] = factor offset of side s,
+// side[F * 4 + 2 s + 1] = its buffer offset.
+__global__ __launch_bounds__(BLOCK) void k_p2p_factors(const FaceTopo *faces, const int *order, const int64_t *side,
+                                                       const double *emap, const double *tab, double *fg) {
+    const int F = blockIdx.x, s = blockIdx.y;
+    const FaceTopo ft = faces[F];
+    if (s == 1 && ft.eR < 0) return;
+    const int e = s ? ft.eR : ft.eL, f = s ? ft.fR : ft.fL, o = s ? ft.orient : 0;
+    const int n = order[e] + 2, npf = n * n;
+    const int k = f / 2, sg = f & 1;
+    double *out = fg + side[(int64_t)F * 4 + 2 * s];
+    const double *X = tab + tab_off_X(n), *W = tab + tab_off_W(n);
+    const int co = s == 1 ? 4 : 1, ao = s == 1 ? 1 : 4;
+    for (int c = threadIdx.x; c < npf; c += BLOCK) {
+        const int fp = own_of_canon(o, n, c), a = fp % n, b = fp / n;
+        double xi[3];
+        xi[k] = sg ? 1.0 : -1.0;
+        xi[k == 0 ? 1 : 0] = X[a];
+        xi[k == 2 ? 1 : 2] = X[b];
+        double r[3][3];
+        const double det = map_adjugate<double>(emap + (int64_t)24 * e, xi[0], xi[1], xi[2], r);
+        const double w = W[a] * W[b];
+        double an[3], js2 = 0.0;
+        for (int cc = 0; cc < 3; ++cc) {
+            const double v = sg ? r[k][cc] : -r[k][cc];
+            js2 += v * v;
+            an[cc] = w * v;
+        }
+        out[c] = w * sqrt(js2);
+        for (int m = 0; m < 3; ++m) {
+            out[(co + m) * npf + c] = (an[0] * r[m][0] + an[1] * r[m][1] + an[2] * r[m][2]) / det;
+            out[(ao + m) * npf + c] = an[m];
+        }
+    }
+}
+
+// Trace stage for the gather-fold apply: own (u, g) of every face side
+// (boundary faces too), and for interior faces this side's u and grad u
+// interpolated to the neighbour's points, with the neighbour's an.
+template <class R, int P>
+__global__ __launch_bounds__(BLOCK) void k_p2p_trace_gf(OpArgs<R> A, int nfm, const int64_t *side, const R *fgp) {
+    using C = Cfg<3, P>;
+    using Ly = Lay<3, P>;
+    constexpr int N = C::N, NFP = C::NFP;
+    if (A.skip && *A.skip) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R *tabs = reinterpret_cast<R *>(smem_raw);
+    R *sm = tabs + C::TABPAD;
+    __shared__ int s_e[C::EPB];
+    __shared__ FaceRef s_face[C::EPB * 6];
+    const int es = elem_stride<3, P>(A.tsz, false);
+    const int nel = block_setup<R, 3, P>(A, tabs, s_e, s_face);
+    element_fields<R, 3, P>(A.x, A.xoff, tabs, tabs + N * C::NP, sm, es, s_e, nel);
+    // work area per direction: [side s][4][N x N] own values on the canonical
+    // grid, then [side s][4][N][nfm] after the first interpolation pass
+    const int vs = 4 * NFP, ts = 4 * N * nfm;
+    for (int k = 0; k < 3; ++k) {
+        // own pair to the buffer, own u and grad u to the work area
+        for (int it = threadIdx.x; it < nel * 2 * NFP; it += BLOCK) {
+            const int el = it / (2 * NFP);
+            int r = it - el * 2 * NFP;
+            const int s = r / NFP, fp = r - s * NFP;
+            const FaceRef fr = s_face[el * 6 + 2 * k + s];
+            const int slot = face_slot(fr.info), si = slot == 1 ? 1 : 0;
+            const int a = fp % N, b = fp / N;
+            const P2PPoint<R> pt = p2p_point<R, P>(A, sm + el * es, s_e[el], k, s, a, b);
+            const int qc = canon_index(face_orient(fr.info), N, a, b);
+            // g = an . grad u with this side's an
+            const R *fg = fgp + side[(int64_t)fr.F * 4 + 2 * si];
+            const int ao = slot == 1 ? 1 : 4;
+            const R g = fg[ao * NFP + qc] * pt.gx[0] + fg[(ao + 1) * NFP + qc] * pt.gx[1] +
+                        fg[(ao + 2) * NFP + qc] * pt.gx[2];
+            R *tb = A.tbuf + side[(int64_t)fr.F * 4 + 2 * si + 1] + (slot == 1 ? 2 * NFP : 0) + qc;
+            tb[0] = pt.u;
+            tb[NFP] = g;
+            if (slot != 2) {
+                R *V = sm + el * es + Ly::T + s * vs + qc;
+                V[0] = pt.u;
+                V[NFP] = pt.gx[0];
+                V[2 * NFP] = pt.gx[1];
+                V[3 * NFP] = pt.gx[2];
+            }
+        }
+        __syncthreads();
+        // first canonical direction: our N points to the neighbour's n_o
+        for (int it = threadIdx.x; it < nel * 2 * 4 * N * nfm; it += BLOCK) {
+            const int el = it / (2 * ts);
+            int r = it - el * 2 * ts;
+            const int s = r / ts;
+            r -= s * ts;
+            const int c = r / (N * nfm);
+            r -= c * N * nfm;
+            const int j2 = r / nfm, t1 = r - j2 * nfm;
+            const FaceRef fr = s_face[el * 6 + 2 * k + s];
+            const int slot = face_slot(fr.info);
+            if (slot == 2) continue;
+            const FaceTopo ft = A.faces[fr.F];
+            const int no = A.order[slot == 0 ? ft.eR : ft.eL] + 2;
+            if (t1 >= no) continue;
+            const R *I = A.tab + tab_off_I(N, no) + t1 * N;   // [no][N]
+            const R *V = sm + el * es + Ly::T + s * vs + c * NFP + j2 * N;
+            R acc = 0;
+            for (int j1 = 0; j1 < N; ++j1) acc += I[j1] * V[j1];
+            sm[el * es + Ly::T + 2 * vs + s * ts + (c * N + j2) * nfm + t1] = acc;
+        }
+        __syncthreads();
+        // second direction, the neighbour's an, into its buffer slot
+        for (int it = threadIdx.x; it < nel * 2 * nfm * nfm; it += BLOCK) {
+            const int el = it / (2 * nfm * nfm);
+            int r = it - el * 2 * nfm * nfm;
+            const int s = r / (nfm * nfm);
+            r -= s * nfm * nfm;
+            const int t2 = r / nfm, t1 = r - t2 * nfm;
+            const FaceRef fr = s_face[el * 6 + 2 * k + s];
+            const int slot = face_slot(fr.info);
+            if (slot == 2) continue;
+            const FaceTopo ft = A.faces[fr.F];
+            const int no = A.order[slot == 0 ? ft.eR : ft.eL] + 2;
+            if (t1 >= no || t2 >= no) continue;
+            const int npo = no * no, co = t1 + no * t2;
+            const R *I = A.tab + tab_off_I(N, no) + t2 * N;
+            R v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const R *T = sm + el * es + Ly::T + 2 * vs + s * ts + c * N * nfm + t1;
+                R acc = 0;
+                for (int j2 = 0; j2 < N; ++j2) acc += I[j2] * T[j2 * nfm];
+                v[c] = acc;
+            }
+            const int so = 1 - slot;   // the neighbour's slot
+            const int64_t fo = side[(int64_t)fr.F * 4 + 2 * so], to = side[(int64_t)fr.F * 4 + 2 * so + 1];
+            const R *an = fgp + fo + (so == 1 ? 1 : 4) * npo + co;
+            const R g = -(an[0] * v[1] + an[npo] * v[2] + an[2 * npo] * v[3]);
+            R *tb = A.tbuf + to + (so == 1 ? 0 : 2 * npo) + co;   // its neighbour slot
+            tb[0] = v[0];
+            tb[npo] = g;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace sipdg

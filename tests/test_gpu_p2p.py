@@ -72,6 +72,29 @@ def test_apply_parity(case):
     assert torch.equal(op.apply(xt), op.apply(xt))
 
 
+def test_structures_agree(case):
+    """The gather-fold path (every face side on its own point set, the
+    neighbour's trace interpolated by its own trace stage) and the general
+    kernels (interpolation inside the apply) give the same operator."""
+    name, mesh, op, om = case
+    xt = torch.tensor(synth.random_coefficients(mesh, 6106), device="cuda")
+    keep = op.variant
+    ys = {}
+    try:
+        for v in ("gather", "gather_fold"):
+            op.variant = v
+            ys[v] = op.apply(xt).cpu().numpy()
+            y32 = op.apply(xt.float()).double().cpu().numpy()
+            assert rel(y32, ys[v]) <= 1e-5, v
+        op.geometry = "map"
+        ys["map"] = op.apply(xt).cpu().numpy()
+        op.geometry = "stored"
+    finally:
+        op.variant = keep
+    assert rel(ys["gather_fold"], ys["gather"]) <= 1e-13
+    assert rel(ys["map"], ys["gather"]) <= 1e-13
+
+
 def test_asymmetry_matches_oracle(case):
     """z^T A x - x^T A z over |z^T A x| + |x^T A z|, GPU against oracle."""
     name, mesh, op, om = case
