@@ -921,7 +921,7 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
     if (x == y) return fail(SIPDG_EINVAL, "x and y must not alias");
     if (reps <= 0) reps = 1;
     hipStream_t st = (hipStream_t)stream;
-    const int per = 2 * (int)h->groups.size();     // launches of one application, at most
+    const int per = 2 * (int)h->groups.size() + 1;   // launches of one application, at most
     if (per > 64) return fail(SIPDG_EINVAL, "too many order groups");
     std::vector<hipEvent_t> ev((size_t)2 * per * reps, nullptr);
     int rc = SIPDG_OK;
