@@ -128,6 +128,13 @@ def test_apply_parity(case):
         assert rel(ym, y_ref) <= 1e-12 and rel(ym32, y_ref) <= 1e-5 and rel(ym, y) <= 1e-13
     finally:
         op.geometry = "stored"
+    # point-to-point flux on the same (split) launches
+    op.flux = "p2p"
+    try:
+        yp = op.apply(xt).cpu().numpy()
+        assert rel(yp, om.apply_p2p(x)) <= 1e-12
+    finally:
+        op.flux = "shared"
 
 
 def test_variants_read_per_point(case):

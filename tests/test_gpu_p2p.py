@@ -139,3 +139,25 @@ def test_entry_points_refuse_nonsymmetric(P):
     m2 = synth.small_mesh(2, 3, 2, seed=84)
     with pytest.raises(P.SipdgError):
         P.SipdgOperator(m2).flux = "p2p"
+
+
+def test_batch_equals_singles(P):
+    """A batched handle under the point-to-point flux (and the modal basis)
+    gives each problem's rows of its own handle."""
+    ms = [synth.small_mesh(3, 2, ("random", 2, 5), seed=89, rotate=True, lam=1.0),
+          synth.small_mesh(3, 3, ("random", 1, 3), seed=90, lam=2.0)]
+    bop = P.SipdgOperator.batch(ms)
+    singles = [P.SipdgOperator(m) for m in ms]
+    off = bop.problem_dof_offsets
+    x = torch.tensor(np.random.default_rng(91).standard_normal(bop.n_dofs), device="cuda")
+    for basis in ("legendre", "modal"):
+        bop.basis = basis
+        bop.flux = "p2p"
+        y = bop.apply(x)
+        for i, op in enumerate(singles):
+            op.basis = basis
+            op.flux = "p2p"
+            yi = op.apply(x[off[i]:off[i + 1]].contiguous())
+            assert float((y[off[i]:off[i + 1]] - yi).norm() / yi.norm()) <= 1e-14, (basis, i)
+            op.flux = "shared"
+        bop.flux = "shared"
