@@ -111,7 +111,7 @@ def p2p_kernel_name(variant, order, stage):
     if variant == "gather":
         return "sipdg::k_p2p_%s<double, %d>" % ("trace" if stage == 1 else "apply", order)
     if stage == 1:
-        return "sipdg::k_p2p_trace_gf<double, %d>" % order
+        return "sipdg::g3::k3t_all<double, 0, true>" if order == 0 else "sipdg::g3::k3t<double, %d, 0, true>" % order
     return "sipdg::g3::k3g<double, %d, 1, 0>" % order
 
 

@@ -168,20 +168,35 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
         const R *fgp = sizeof(R) == 8 ? (const R *)c->d_fgeo_p2p64 : (const R *)c->d_fgeo_p2p32;
         for (int stage = 1; stage <= 2; ++stage) {
             if (!(stages & stage)) continue;
+            // trace stage: one wavefront launch for the orders <= 6 of the
+            // persistent list, one per remaining group
+            if (stage == 1 && c->pcount > 0) {
+                f3::Args3 A3;
+                f3::Data3<R> D3;
+                fast_args<R>(c, c->groups[0], x, y, pb, skip, false, A3, D3);
+                g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
+                           A3.skip, c->d_pdesc, c->d_pfdesc_p2p, c->basis, c->d_p2p_side};
+                g3::Data<R> D{D3.vgeo, fgp, D3.lam, D3.tau, D3.tab, D3.x, D3.y, pb, egeo_of<R>(c), emap_of<R>(c)};
+                rec_mark(rec, 1, -1, false, st);
+                hipError_t e = launch_gfold3d_trace_all<R>(A, D, st);
+                rec_mark(rec, 1, -1, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string("point-to-point trace: ") + hipGetErrorString(e));
+            }
             for (size_t gi = 0; gi < c->groups.size(); ++gi) {
                 const Group &g = c->groups[gi];
+                if (stage == 1 && c->pcount > 0 && g.P <= 6 && g.nfmax <= 8) continue;
                 rec_mark(rec, stage, (int)gi, false, st);
                 hipError_t e = hipSuccess;
+                f3::Args3 A3;
+                f3::Data3<R> D3;
+                fast_args<R>(c, g, x, y, pb, skip, false, A3, D3);
+                g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
+                           A3.toff, A3.skip, g.d_desc, g.d_fdesc_p2p, c->basis, c->d_p2p_side};
+                g3::Data<R> D{D3.vgeo, fgp, D3.lam, D3.tau, D3.tab, D3.x, D3.y, pb, egeo_of<R>(c), emap_of<R>(c)};
                 if (stage == 1) {
-                    OpArgs<R> A = make_args<R>(c, g, x, y, pb, skip);
-                    e = launch_p2p_trace_gf<R>(g.P, A, g.nfmax, c->d_p2p_side, fgp, st);
+                    e = launch_gfold3d<R>(g.P, 0, g.P + 2, A, D, st);
                 } else {
-                    f3::Args3 A3;
-                    f3::Data3<R> D3;
-                    fast_args<R>(c, g, x, y, pb, skip, false, A3, D3);
-                    g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff,
-                               A3.toff, A3.skip, g.d_desc, g.d_fdesc_p2p, c->basis};
-                    g3::Data<R> D{D3.vgeo, fgp, D3.lam, D3.tau, D3.tab, D3.x, D3.y, pb, egeo_of<R>(c), emap_of<R>(c)};
                     const int mode = c->geo_map ? 4 : 1;
                     if (g.split) {
                         g3::Args Aa = A, Ad = A;
@@ -451,7 +466,8 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
                     c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32,
-                    c->d_tbuf_p2p, c->d_p2p_side, c->d_fgeo_p2p64, c->d_fgeo_p2p32};
+                    c->d_tbuf_p2p, c->d_p2p_side, c->d_fgeo_p2p64, c->d_fgeo_p2p32,
+                    c->d_pfdesc_p2p};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->d_pdesc) (void)hipFree(c->d_pdesc);
@@ -1018,11 +1034,12 @@ static int build_p2p(sipdg_ctx *h) {
     if (rc) return rc;
     HIPCHK(launch_p2p_factors(nf, h->d_faces, h->d_order, h->d_p2p_side, h->d_emap64, h->d_tab64, h->d_fgeo_p2p64, 0));
     HIPCHK(launch_cast_f32(h->d_fgeo_p2p64, h->d_fgeo_p2p32, std::max<int64_t>(fo, 1), 0));
-    for (Group &g : h->groups) {
-        std::vector<ElemDesc> desc(g.count);
-        HIPCHK(hipMemcpy(desc.data(), g.d_desc, sizeof(ElemDesc) * g.count, hipMemcpyDeviceToHost));
-        std::vector<FaceDesc> fd((size_t)g.count * 6);
-        for (int i = 0; i < g.count; ++i) {
+    // face descriptors in the launch order of a descriptor list
+    auto p2p_fdesc = [&](const ElemDesc *d_desc, int count, FaceDesc **out) -> int {
+        std::vector<ElemDesc> desc(count);
+        HIPCHK(hipMemcpy(desc.data(), d_desc, sizeof(ElemDesc) * count, hipMemcpyDeviceToHost));
+        std::vector<FaceDesc> fd((size_t)count * 6);
+        for (int i = 0; i < count; ++i) {
             const int e = desc[i].e, n = order[e] + 2;
             for (int f = 0; f < 6; ++f) {
                 const FaceRef fr = eface[(size_t)e * 6 + f];
@@ -1032,7 +1049,14 @@ static int build_p2p(sipdg_ctx *h) {
                                                  fr.F, info};
             }
         }
-        rc = upload(&g.d_fdesc_p2p, fd);
+        return upload(out, fd);
+    };
+    for (Group &g : h->groups) {
+        rc = p2p_fdesc(g.d_desc, g.count, &g.d_fdesc_p2p);
+        if (rc) return rc;
+    }
+    if (h->pcount > 0) {
+        rc = p2p_fdesc(h->d_pdesc, h->pcount, &h->d_pfdesc_p2p);
         if (rc) return rc;
     }
     HIPCHK(hipDeviceSynchronize());

@@ -139,6 +139,7 @@ struct sipdg_ctx {
     bool fast_ok0 = false, gfold_ok0 = false;   // structures the mesh allows (Legendre basis)
     void *d_tbuf_p2p = nullptr;   // point-to-point trace buffer (FP64 units: 2 x tbuf_len)
     int64_t *d_p2p_side = nullptr;           // [nf][2][factor offset, buffer offset] (gather-fold p2p)
+    sipdg::FaceDesc *d_pfdesc_p2p = nullptr; // point-to-point face descriptors of the persistent list
     double *d_fgeo_p2p64 = nullptr;          // per face side: a, C, an on its own grid
     float *d_fgeo_p2p32 = nullptr;
     double *d_tau0 = nullptr;

@@ -104,6 +104,7 @@ struct Args {
     const ElemDesc *desc;    // [count]
     const FaceDesc *fdesc;   // [count][6]
     int basis = 0;           // host side: 0 Legendre, 1 modified C0 modal (trace kernels)
+    const int64_t *side = nullptr;   // point-to-point trace: [nf][2][factor, buffer offset]
 };
 
 template <class R>
@@ -119,6 +120,28 @@ struct Data {
     const R *__restrict__ egeo;   // [ne][8]: G~ (00 01 02 11 12 22), |J| of affine elements
     const R *__restrict__ emap;   // [ne][24]: trilinear map coefficients c1..c7 (x, y, z), pad
 };
+
+// Rows of adj(J) and det J of the trilinear map with coefficients c1..c7
+// (each x, y, z) at xi: the columns of J are dx/dxi_k, the rows of adj(J) the
+// cross products of the columns.
+template <class R>
+__device__ __forceinline__ R map_adjugate3(const R *cm, R x0, R x1, R x2, R r[3][3]) {
+    R j0[3], j1[3], j2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        j0[c] = cm[c] + cm[9 + c] * x1 + cm[12 + c] * x2 + cm[18 + c] * x1 * x2;
+        j1[c] = cm[3 + c] + cm[9 + c] * x0 + cm[15 + c] * x2 + cm[18 + c] * x0 * x2;
+        j2[c] = cm[6 + c] + cm[12 + c] * x0 + cm[15 + c] * x1 + cm[18 + c] * x0 * x1;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        r[0][c] = j1[c1] * j2[c2] - j1[c2] * j2[c1];
+        r[1][c] = j2[c1] * j0[c2] - j2[c2] * j0[c1];
+        r[2][c] = j0[c1] * j1[c2] - j0[c2] * j1[c1];
+    }
+    return j0[0] * r[0][0] + j0[1] * r[0][1] + j0[2] * r[0][2];
+}
 
 // Tables are read through the constant address space: the compiler may then
 // assume no store of the kernel writes them and reads wave-uniform entries
@@ -1222,7 +1245,7 @@ struct TSz {
     static constexpr int TOTAL = XS + NU + NW + BT;
 };
 
-template <class R, int P, int BASIS = 0>
+template <class R, int P, int BASIS = 0, bool P2P = false>
 __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
     using T = TSz<P>;
     constexpr int NP = T::NP, N = T::N, WG = T::W, SG = Geo<P>::S, NM = NP * NP * NP;
@@ -1234,6 +1257,23 @@ __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int bl
     const int l = threadIdx.x, a = gx<P>(l), b = gy<P>(l);
     const bool ln = a < NP && b < NP;
     const MetaV<R> meta = load_meta<R, 0>(A, D, blk);
+    // point-to-point flux (every face side on its own point set): lane f < 6
+    // holds the neighbour's n, slot and factor / buffer offsets of face f
+    int nb_no = 0, nb_so = 0;
+    int64_t nb_fo = 0, nb_to = 0;
+    if constexpr (P2P) {
+        if ((l & 63) < 6) {
+            const FaceDesc fr = A.fdesc[(int64_t)blk * 6 + (l & 63)];
+            const int slot = face_slot(fr.info);
+            if (slot != 2) {
+                const FaceTopo ft = A.faces[fr.F];
+                nb_so = 1 - slot;
+                nb_no = A.order[slot == 0 ? ft.eR : ft.eL] + 2;
+                nb_fo = A.side[(int64_t)fr.F * 4 + 2 * nb_so];
+                nb_to = A.side[(int64_t)fr.F * 4 + 2 * nb_so + 1];
+            }
+        }
+    }
     // the coefficients (coalesced) and the trace tables into LDS: every load
     // issued before the first store
     constexpr int XIT = (NM + WG - 1) / WG, BIT = (T::BT / 2 + WG - 1) / WG;
@@ -1353,10 +1393,12 @@ __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int bl
         }
         __syncthreads();
         // second contraction, along b: lane (t1, t2); g = C . grad_xi u; store
+        R pv[2][4];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const FaceU<R> &fu = tu[2 * k + s];
             const FaceD<R> &fd = td[2 * k + s];
+            pv[s][0] = pv[s][1] = pv[s][2] = pv[s][3] = R(0);
             if (a < fu.nf && b < fu.nf) {
                 const R *bf = BT + T::bt_off(fu.nf) + NP * b, *dbf = bf + fu.nf * NP;
                 const R *w0 = NW + 3 * s * WG + a, *w0d = w0 + WG, *w1 = w0 + 2 * WG;
@@ -1372,32 +1414,96 @@ __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int bl
                 R *__restrict__ tb = D.tbuf + fu.to + tb_side(fu.slot) * 2 * fu.npf + fd.qc;
                 tb[0] = vu;
                 tb[fu.npf] = fd.Ck * vdk + fd.Ca * vda + fd.Cb * vdb;
+                pv[s][0] = vu;
+                pv[s][1] = vda;
+                pv[s][2] = vdb;
+                pv[s][3] = vdk;
             }
+        }
+        if constexpr (P2P) {
+            // this side's u and grad_x u (own points, canonical order) to the
+            // neighbour's points: two passes through LDS (I(n -> n_o)); then
+            // (I u, -an_o . I grad u) into the neighbour's slot
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int f = 2 * k + s;
+                const int no = rl32(nb_no, f);
+                if (no == 0) continue;   // boundary face (uniform)
+                __syncthreads();
+                if (a < N && b < N) {
+                    const R *X = D.tab + tab_off_X(N);
+                    R xi[3], d[3];
+                    xi[k] = s ? R(1) : R(-1);
+                    xi[dir_a(k)] = X[a];
+                    xi[dir_b(k)] = X[b];
+                    d[k] = pv[s][3];
+                    d[dir_a(k)] = pv[s][1];
+                    d[dir_b(k)] = pv[s][2];
+                    R r[3][3];
+                    const R inv = R(1) / map_adjugate3<R>(D.emap + (int64_t)24 * ed.e, xi[0], xi[1], xi[2], r);
+                    const int qc = td[f].qc;
+                    NU[qc] = pv[s][0];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        NU[(1 + c) * N * N + qc] = (r[0][c] * d[0] + r[1][c] * d[1] + r[2][c] * d[2]) * inv;
+                }
+                __syncthreads();
+                const R *I = D.tab + tab_off_I(N, no);   // [no][N]
+                for (int i = l; i < N * no; i += WG) {
+                    const int t1 = i % no, j2 = i / no;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        R acc = 0;
+#pragma unroll
+                        for (int j1 = 0; j1 < N; ++j1) acc += I[t1 * N + j1] * NU[c * N * N + j2 * N + j1];
+                        NW[c * N * no + j2 * no + t1] = acc;
+                    }
+                }
+                __syncthreads();
+                const int so = rl32(nb_so, f), npo = no * no;
+                const int64_t fo = rl64(nb_fo, f), to = rl64(nb_to, f);
+                for (int i = l; i < npo; i += WG) {
+                    const int t1 = i % no, t2 = i / no;
+                    R w[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        R acc = 0;
+#pragma unroll
+                        for (int j2 = 0; j2 < N; ++j2) acc += I[t2 * N + j2] * NW[c * N * no + j2 * no + t1];
+                        w[c] = acc;
+                    }
+                    const R *an = D.fgeo + fo + (so == 1 ? 1 : 4) * npo + i;
+                    R *__restrict__ tb = D.tbuf + to + (so == 1 ? 0 : 2 * npo) + i;
+                    tb[0] = w[0];
+                    tb[npo] = -(an[0] * w[1] + an[npo] * w[2] + an[2 * npo] * w[3]);
+                }
+            }
+            __syncthreads();
         }
     }
 }
 
-template <class R, int P, int BASIS = 0>
+template <class R, int P, int BASIS = 0, bool P2P = false>
 __global__ __launch_bounds__(Geo<P>::W) void k3t(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    k3t_elem<R, P, BASIS>(A, D, blockIdx.x, smem_raw);
+    k3t_elem<R, P, BASIS, P2P>(A, D, blockIdx.x, smem_raw);
 }
 
 // Trace stage of every element of order <= 6 (traces <= 8 x 8) in one launch:
 // block b takes element b of A.desc / A.fdesc, its order in ElemDesc::pad.
-template <class R, int BASIS = 0>
+template <class R, int BASIS = 0, bool P2P = false>
 __global__ __launch_bounds__(W) void k3t_all(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;
     switch (A.desc[i].pad & ELEM_ORDER_MASK) {
-    case 1: k3t_elem<R, 1, BASIS>(A, D, i, smem_raw); break;
-    case 2: k3t_elem<R, 2, BASIS>(A, D, i, smem_raw); break;
-    case 3: k3t_elem<R, 3, BASIS>(A, D, i, smem_raw); break;
-    case 4: k3t_elem<R, 4, BASIS>(A, D, i, smem_raw); break;
-    case 5: k3t_elem<R, 5, BASIS>(A, D, i, smem_raw); break;
-    default: k3t_elem<R, 6, BASIS>(A, D, i, smem_raw); break;
+    case 1: k3t_elem<R, 1, BASIS, P2P>(A, D, i, smem_raw); break;
+    case 2: k3t_elem<R, 2, BASIS, P2P>(A, D, i, smem_raw); break;
+    case 3: k3t_elem<R, 3, BASIS, P2P>(A, D, i, smem_raw); break;
+    case 4: k3t_elem<R, 4, BASIS, P2P>(A, D, i, smem_raw); break;
+    case 5: k3t_elem<R, 5, BASIS, P2P>(A, D, i, smem_raw); break;
+    default: k3t_elem<R, 6, BASIS, P2P>(A, D, i, smem_raw); break;
     }
 }
 __host__ __device__ constexpr int lds_trace_all() {

@@ -18,7 +18,9 @@ hipError_t gfold_p(int mode, int nfmax, const g3::Args &A, const g3::Data<double
     if (A.count <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * g3::lds_mode<P>(mode >= 3 ? 1 : mode);
     const dim3 blk(g3::Geo<P>::W);
-    if (mode == 0 && A.basis) hipLaunchKernelGGL((g3::k3t<double, P, 1>), dim3(A.count), blk, lds, st, A, D);
+    if (mode == 0 && A.side && A.basis) hipLaunchKernelGGL((g3::k3t<double, P, 1, true>), dim3(A.count), blk, lds, st, A, D);
+    else if (mode == 0 && A.side) hipLaunchKernelGGL((g3::k3t<double, P, 0, true>), dim3(A.count), blk, lds, st, A, D);
+    else if (mode == 0 && A.basis) hipLaunchKernelGGL((g3::k3t<double, P, 1>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 0) hipLaunchKernelGGL((g3::k3t<double, P>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 1) hipLaunchKernelGGL((g3::k3g<double, P, 1>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 3) hipLaunchKernelGGL((g3::k3g<double, P, 1, g3::GEO_AFFINE>), dim3(A.count), blk, lds, st, A, D);
@@ -65,7 +67,9 @@ template <>
 hipError_t launch_gfold3d_trace_all<double>(const g3::Args &A, const g3::Data<double> &D, hipStream_t st) {
     if (A.count <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * g3::lds_trace_all();
-    if (A.basis) hipLaunchKernelGGL((g3::k3t_all<double, 1>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    if (A.side && A.basis) hipLaunchKernelGGL((g3::k3t_all<double, 1, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    else if (A.side) hipLaunchKernelGGL((g3::k3t_all<double, 0, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    else if (A.basis) hipLaunchKernelGGL((g3::k3t_all<double, 1>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else hipLaunchKernelGGL((g3::k3t_all<double>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     return hipGetLastError();
 }

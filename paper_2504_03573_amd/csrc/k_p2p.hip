@@ -24,16 +24,6 @@ hipError_t p2p_p(int stage, const OpArgs<R> &A, int nfm, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <class R, int P>
-hipError_t p2p_gf_p(const OpArgs<R> &A, int nfm, const int64_t *side, const R *fgp, hipStream_t st) {
-    using C = Cfg<3, P>;
-    if (A.count <= 0) return hipSuccess;
-    const int blocks = (A.count + C::EPB - 1) / C::EPB;
-    const size_t lds = lds_bytes<3, P>(A.tsz, false, sizeof(R));
-    ensure_lds(k_p2p_trace_gf<R, P>, lds);
-    hipLaunchKernelGGL((k_p2p_trace_gf<R, P>), dim3(blocks), dim3(BLOCK), lds, st, A, nfm, side, fgp);
-    return hipGetLastError();
-}
 }  // namespace
 
 template <>
@@ -55,22 +45,6 @@ hipError_t launch_p2p_factors(int64_t nfaces, const FaceTopo *faces, const int *
     if (nfaces <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_p2p_factors, dim3((unsigned)nfaces, 2), dim3(BLOCK), 0, st, faces, order, side, emap, tab, fg);
     return hipGetLastError();
-}
-
-template <>
-hipError_t launch_p2p_trace_gf<double>(int P, const OpArgs<double> &A, int nfm, const int64_t *side,
-                                       const double *fgp, hipStream_t st) {
-#define CALL(p) p2p_gf_p<double, p>(A, nfm, side, fgp, st)
-    SIPDG_DISPATCH_P(P, CALL)
-#undef CALL
-}
-
-template <>
-hipError_t launch_p2p_trace_gf<float>(int P, const OpArgs<float> &A, int nfm, const int64_t *side,
-                                      const float *fgp, hipStream_t st) {
-#define CALL(p) p2p_gf_p<float, p>(A, nfm, side, fgp, st)
-    SIPDG_DISPATCH_P(P, CALL)
-#undef CALL
 }
 
 }  // namespace sipdg

@@ -14,14 +14,11 @@ hipError_t launch_op(int dim, int P, int kind, const OpArgs<R> &A, int nfm, hipS
 // tsz must be work_size(nfm).
 template <class R>
 hipError_t launch_p2p(int P, int stage, const OpArgs<R> &A, int nfm, hipStream_t st);
-// Point-to-point flux through the gather-fold apply: per-side factors (FP64,
-// every face side) and the trace stage that writes each side's own pair and
-// its trace interpolated to the neighbour's points.  side: [nf][2][fo, to].
+// Point-to-point flux through the gather-fold kernels: per-side factors
+// (FP64, every face side; side: [nf][2][factor offset, buffer offset]).
 hipError_t launch_p2p_factors(int64_t nfaces, const FaceTopo *faces, const int *order, const int64_t *side,
                               const double *emap, const double *tab, double *fg, hipStream_t st);
-template <class R>
-hipError_t launch_p2p_trace_gf(int P, const OpArgs<R> &A, int nfm, const int64_t *side, const R *fgp,
-                               hipStream_t st);
+
 int work_size_for(int dim, int P, int nfm);
 size_t lds_for(int dim, int P, int tsz, bool lift, size_t rsize);
 int elems_per_block(int dim, int P);

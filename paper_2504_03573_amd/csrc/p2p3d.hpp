@@ -81,35 +81,6 @@ __device__ __forceinline__ P2PPoint<R> p2p_point(const OpArgs<R> &A, const R *sm
     return pt;
 }
 
-// The same from u alone: grad_xi u at the face point by the collocation
-// derivative along each direction (3 n LDS reads), so the trace stage needs
-// no volume gradient.  Dt: D(n) [n][n] in LDS.
-template <class R, int P>
-__device__ __forceinline__ P2PPoint<R> p2p_point_u(const OpArgs<R> &A, const R *sm, const R *Dt, int e, int k, int s,
-                                                   int a, int b) {
-    using C = Cfg<3, P>;
-    using Ly = Lay<3, P>;
-    constexpr int N = C::N;
-    P2PPoint<R> pt;
-    const int q = face_point<3, N>(k, s, a, b);
-    const int i0 = q % N, i1 = (q / N) % N, i2 = q / (N * N);
-    const R *X = A.tab + tab_off_X(N);
-    pt.det = map_adjugate<R>(A.emap + (int64_t)24 * e, X[i0], X[i1], X[i2], pt.r);
-    const R *U = sm + Ly::U;
-    pt.u = U[q];
-    R d0 = 0, d1 = 0, d2 = 0;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        d0 += Dt[i0 * N + j] * U[q + (j - i0)];
-        d1 += Dt[i1 * N + j] * U[q + (j - i1) * N];
-        d2 += Dt[i2 * N + j] * U[q + (j - i2) * N * N];
-    }
-    const R inv = R(1) / pt.det;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) pt.gx[c] = (pt.r[0][c] * d0 + pt.r[1][c] * d1 + pt.r[2][c] * d2) * inv;
-    return pt;
-}
-
 // K1: u and grad_x u at the own face points of every interior face side.
 // Buffer: face F at 2 toff[F], side slot at + slot 4 nf^2, component c at
 // + c nf^2, canonical index on the side's own n x n grid.
@@ -277,9 +248,9 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_apply(OpArgs<R> A, int nfm) {
 //            other side (the apply reads C at 1 or 4 npf by slot);
 //   buffer   own (u, g = an . grad u) and the neighbour's (u, -an . I grad u_o),
 //            both on this side's grid, at the slots the apply reads.
-// The trace kernel below writes both: its own pair, and its trace
-// interpolated to the neighbour's points for the neighbour (Sec. 3.3,
-// ScatrInterp), using the neighbour's an.
+// The gather-fold trace kernel (k3t_elem with its point-to-point flag) writes
+// both: its own pair, and its trace interpolated to the neighbour's points
+// for the neighbour (Sec. 3.3, ScatrInterp), using the neighbour's an.
 
 // Factors of every face side (one block per side, FP64); boundary faces have
 // one side (slot 0 layout).  side[F * 4 + 2 s] = factor offset of side s,
@@ -315,129 +286,6 @@ __global__ __launch_bounds__(BLOCK) void k_p2p_factors(const FaceTopo *faces, co
             out[(co + m) * npf + c] = (an[0] * r[m][0] + an[1] * r[m][1] + an[2] * r[m][2]) / det;
             out[(ao + m) * npf + c] = an[m];
         }
-    }
-}
-
-// Trace stage for the gather-fold apply: own (u, g) of every face side
-// (boundary faces too), and for interior faces this side's u and grad u
-// interpolated to the neighbour's points, with the neighbour's an.
-template <class R, int P>
-__global__ __launch_bounds__(BLOCK) void k_p2p_trace_gf(OpArgs<R> A, int nfm, const int64_t *side, const R *fgp) {
-    using C = Cfg<3, P>;
-    using Ly = Lay<3, P>;
-    constexpr int N = C::N, NFP = C::NFP;
-    if (A.skip && *A.skip) return;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    R *tabs = reinterpret_cast<R *>(smem_raw);
-    R *sm = tabs + C::TABPAD;
-    __shared__ int s_e[C::EPB];
-    __shared__ FaceRef s_face[C::EPB * 6];
-    const int es = elem_stride<3, P>(A.tsz, false);
-    const int nel = block_setup<R, 3, P>(A, tabs, s_e, s_face);
-    const R *Dt = tabs + N * C::NP;
-    // per face side of the block: own factor / buffer offsets, and the
-    // neighbour's n, factor and buffer offsets (one round of dependent loads)
-    __shared__ int64_t s_own[C::EPB * 6][2], s_nb[C::EPB * 6][2];
-    __shared__ int s_no[C::EPB * 6];
-    if (threadIdx.x < nel * 6) {
-        const FaceRef fr = s_face[threadIdx.x];
-        const int slot = face_slot(fr.info), si = slot == 1 ? 1 : 0;
-        s_own[threadIdx.x][0] = side[(int64_t)fr.F * 4 + 2 * si];
-        s_own[threadIdx.x][1] = side[(int64_t)fr.F * 4 + 2 * si + 1];
-        if (slot != 2) {
-            const FaceTopo ft = A.faces[fr.F];
-            s_no[threadIdx.x] = A.order[slot == 0 ? ft.eR : ft.eL] + 2;
-            s_nb[threadIdx.x][0] = side[(int64_t)fr.F * 4 + 2 * (1 - slot)];
-            s_nb[threadIdx.x][1] = side[(int64_t)fr.F * 4 + 2 * (1 - slot) + 1];
-        } else {
-            s_no[threadIdx.x] = 0;
-            s_nb[threadIdx.x][0] = s_nb[threadIdx.x][1] = 0;
-        }
-    }
-    // u only: the face gradients come from u along each direction
-    element_fields<R, 3, P, false>(A.x, A.xoff, tabs, Dt, sm, es, s_e, nel);
-    // work area per direction: [side s][4][N x N] own values on the canonical
-    // grid, then [side s][4][N][nfm] after the first interpolation pass
-    const int vs = 4 * NFP, ts = 4 * N * nfm;
-    for (int k = 0; k < 3; ++k) {
-        // own pair to the buffer, own u and grad u to the work area
-        for (int it = threadIdx.x; it < nel * 2 * NFP; it += BLOCK) {
-            const int el = it / (2 * NFP);
-            int r = it - el * 2 * NFP;
-            const int s = r / NFP, fp = r - s * NFP;
-            const int fi = el * 6 + 2 * k + s;
-            const FaceRef fr = s_face[fi];
-            const int slot = face_slot(fr.info);
-            const int a = fp % N, b = fp / N;
-            const P2PPoint<R> pt = p2p_point_u<R, P>(A, sm + el * es, Dt, s_e[el], k, s, a, b);
-            const int qc = canon_index(face_orient(fr.info), N, a, b);
-            // g = an . grad u with this side's an
-            const R *fg = fgp + s_own[fi][0];
-            const int ao = slot == 1 ? 1 : 4;
-            const R g = fg[ao * NFP + qc] * pt.gx[0] + fg[(ao + 1) * NFP + qc] * pt.gx[1] +
-                        fg[(ao + 2) * NFP + qc] * pt.gx[2];
-            R *tb = A.tbuf + s_own[fi][1] + (slot == 1 ? 2 * NFP : 0) + qc;
-            tb[0] = pt.u;
-            tb[NFP] = g;
-            if (slot != 2) {
-                R *V = sm + el * es + Ly::T + s * vs + qc;
-                V[0] = pt.u;
-                V[NFP] = pt.gx[0];
-                V[2 * NFP] = pt.gx[1];
-                V[3 * NFP] = pt.gx[2];
-            }
-        }
-        __syncthreads();
-        // first canonical direction: our N points to the neighbour's n_o
-        for (int it = threadIdx.x; it < nel * 2 * 4 * N * nfm; it += BLOCK) {
-            const int el = it / (2 * ts);
-            int r = it - el * 2 * ts;
-            const int s = r / ts;
-            r -= s * ts;
-            const int c = r / (N * nfm);
-            r -= c * N * nfm;
-            const int j2 = r / nfm, t1 = r - j2 * nfm;
-            const int fi = el * 6 + 2 * k + s;
-            const int no = s_no[fi];
-            if (no == 0) continue;   // boundary face
-            if (t1 >= no) continue;
-            const R *I = A.tab + tab_off_I(N, no) + t1 * N;   // [no][N]
-            const R *V = sm + el * es + Ly::T + s * vs + c * NFP + j2 * N;
-            R acc = 0;
-            for (int j1 = 0; j1 < N; ++j1) acc += I[j1] * V[j1];
-            sm[el * es + Ly::T + 2 * vs + s * ts + (c * N + j2) * nfm + t1] = acc;
-        }
-        __syncthreads();
-        // second direction, the neighbour's an, into its buffer slot
-        for (int it = threadIdx.x; it < nel * 2 * nfm * nfm; it += BLOCK) {
-            const int el = it / (2 * nfm * nfm);
-            int r = it - el * 2 * nfm * nfm;
-            const int s = r / (nfm * nfm);
-            r -= s * nfm * nfm;
-            const int t2 = r / nfm, t1 = r - t2 * nfm;
-            const int fi = el * 6 + 2 * k + s;
-            const int no = s_no[fi];
-            if (no == 0) continue;   // boundary face
-            if (t1 >= no || t2 >= no) continue;
-            const int npo = no * no, co = t1 + no * t2;
-            const R *I = A.tab + tab_off_I(N, no) + t2 * N;
-            R v[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const R *T = sm + el * es + Ly::T + 2 * vs + s * ts + c * N * nfm + t1;
-                R acc = 0;
-                for (int j2 = 0; j2 < N; ++j2) acc += I[j2] * T[j2 * nfm];
-                v[c] = acc;
-            }
-            const int so = 1 - face_slot(s_face[fi].info);   // the neighbour's slot
-            const int64_t fo = s_nb[fi][0], to = s_nb[fi][1];
-            const R *an = fgp + fo + (so == 1 ? 1 : 4) * npo + co;
-            const R g = -(an[0] * v[1] + an[npo] * v[2] + an[2 * npo] * v[3]);
-            R *tb = A.tbuf + to + (so == 1 ? 0 : 2 * npo) + co;   // its neighbour slot
-            tb[0] = v[0];
-            tb[npo] = g;
-        }
-        __syncthreads();
     }
 }
 
