@@ -92,7 +92,8 @@ def kernel_name(variant, order, stage=2, geo_map=False):
     """Kernel symbol (as rocprofv3 prints it, FP64) of one launch."""
     if variant == "gather_fold":
         if stage == 1:
-            return "sipdg::g3::k3t_all<double, 0>" if order == 0 else "sipdg::g3::k3t<double, %d, 0>" % order
+            return ("sipdg::g3::k3t_all<double, 0, false>" if order == 0
+                    else "sipdg::g3::k3t<double, %d, 0, false>" % order)
         return "sipdg::g3::k3g<double, %d, 1, %d>" % (order, 2 if geo_map else 0)
     if variant == "gather_fold_persistent" and order == 0:
         return "sipdg::g3::k3g_persistent<double, %d>" % (0 if stage == 1 else 1)
