@@ -66,6 +66,8 @@ class _OMesh(ctypes.Structure):
         ("gll_x", ctypes.c_void_p),
         ("gll_w", ctypes.c_void_p),
         ("basis", ctypes.c_int),
+        ("vol_x", ctypes.c_void_p),
+        ("vol_w", ctypes.c_void_p),
     ]
 
 
@@ -133,20 +135,23 @@ def gll(n: int):
 
 
 def gauss_legendre(n: int):
+    """Gauss-Legendre nodes and weights (NumPy's Golub-Welsch routine)."""
     return np.polynomial.legendre.leggauss(n)
 
 
-def _tables():
+def _tables(rule):
     X = np.zeros((OR_MAXN + 1, OR_MAXN))
     W = np.zeros((OR_MAXN + 1, OR_MAXN))
     for n in range(2, OR_MAXN + 1):
-        x, w = gll(n)
+        x, w = rule(n)
         X[n, :n] = x
         W[n, :n] = w
     return X, W
 
 
-_GLL_X, _GLL_W = _tables()
+_GLL_X, _GLL_W = _tables(gll)
+_GL_X, _GL_W = _tables(gauss_legendre)
+POINTS = {"gll": (_GLL_X, _GLL_W), "gl": (_GL_X, _GL_W)}
 
 
 # ---------------------------------------------------------------- topology
@@ -175,9 +180,11 @@ def _face_corner_ids(ev_e: np.ndarray, dim: int, f: int):
 class OracleMesh:
     """A mesh prepared for the oracle (neighbours, owners, face maps)."""
 
-    def __init__(self, mesh, basis: str = "legendre"):
+    def __init__(self, mesh, basis: str = "legendre", points: str = "gll"):
         self.mesh = mesh
         self.basis = basis
+        self.points = points
+        vx, vw = POINTS[points]
         d = mesh.dim
         ne = mesh.n_elems
         nf = 2 * d
@@ -240,7 +247,7 @@ class OracleMesh:
             nb=self.nb.ctypes.data, nb_face=self.nb_face.ctypes.data,
             owner=self.owner.ctypes.data, amap=self.amap.ctypes.data,
             gll_x=_GLL_X.ctypes.data, gll_w=_GLL_W.ctypes.data,
-            basis=BASES[basis])
+            basis=BASES[basis], vol_x=vx.ctypes.data, vol_w=vw.ctypes.data)
 
     def set_lambda(self, lam):
         self.lam[:] = np.asarray(lam, dtype=np.float64)
@@ -400,6 +407,10 @@ class OracleMesh:
         return x, it, float(np.linalg.norm(b - self.apply(x))) / nb
 
 
-def prepare(mesh, basis: str = "legendre") -> OracleMesh:
-    """basis: "legendre" (orthogonal) or "modal" (modified C0, Table 1)."""
-    return OracleMesh(mesh, basis)
+def prepare(mesh, basis: str = "legendre", points: str = "gll") -> OracleMesh:
+    """basis: "legendre" (orthogonal) or "modal" (modified C0, Table 1).
+    points: the operator's volume quadrature, "gll" (p + 2 Gauss-Lobatto
+    points per direction) or "gl" (p + 2 Gauss points, which leave out the
+    element boundary, Sec. 3.2); the faces use the trace's GLL points
+    either way."""
+    return OracleMesh(mesh, basis, points)

@@ -12,7 +12,9 @@
  *     (Sec. 2.1, expansion eq. and tensor basis eq.): the orthogonal
  *     (Legendre) basis of Table 1, or its modified C0 modal basis;
  *   - tensor Gauss-Lobatto-Legendre quadrature with the Jacobian determinant
- *     (Sec. 2.1, inner-product eq.), p+2 points per direction (Sec. 5.2);
+ *     (Sec. 2.1, inner-product eq.), p+2 points per direction (Sec. 5.2), or
+ *     for the volume terms Gauss-Legendre points (Sec. 3.2, the point sets
+ *     that do not contain the element boundary);
  *   - the element-wise SIPG form (Sec. 2.2, eq. IP) with the average and
  *     jump operators of Sec. 2.2; summing it over elements gives the primal
  *     form (eq. primal);
@@ -59,6 +61,8 @@ typedef struct {
     const double *gll_x;    /* [OR_MAXN+1][OR_MAXN] nodes, row n holds n nodes */
     const double *gll_w;    /* same shape, weights */
     int basis;              /* 0: Legendre (orthogonal), 1: modified C0 modal */
+    const double *vol_x;    /* volume quadrature of the operator, same shape: */
+    const double *vol_w;    /* the GLL tables, or Gauss-Legendre nodes/weights */
 } omesh;
 
 /* Legendre polynomials P_0..P_p and their derivatives at x (Bonnet's
@@ -286,7 +290,10 @@ static void element_rows(const omesh *m, long e, const double *x, double *y, int
 {
     int d = m->dim, p = m->order[e], n = p + 2;
     int nm = ipow(p + 1, d), nq = ipow(n, d);
-    const double *gx = m->gll_x + n * OR_MAXN, *gw = m->gll_w + n * OR_MAXN;
+    /* volume quadrature: n = p + 2 points per direction, GLL or Gauss (the
+     * latter leaves out the element boundary; the faces keep the trace's
+     * own GLL points either way) */
+    const double *gx = m->vol_x + n * OR_MAXN, *gw = m->vol_w + n * OR_MAXN;
     const double *xe = x ? x + m->dof_off[e] : NULL;
     double *ye = y + m->dof_off[e];
     double lam = m->lambda[e];
