@@ -183,7 +183,7 @@ class OracleMesh:
     def __init__(self, mesh, basis: str = "legendre", points: str = "gll"):
         self.mesh = mesh
         self.basis = basis
-        self.points = points
+        self.vol_points = points
         vx, vw = POINTS[points]
         d = mesh.dim
         ne = mesh.n_elems
