@@ -247,6 +247,36 @@ int sipdg_get_variant(sipdg_handle h, int *variant);
 int sipdg_set_basis(sipdg_handle h, int basis);
 int sipdg_get_basis(sipdg_handle h, int *basis);
 
+/* Volume quadrature points (Sec. 3.2: point sets that contain the element
+ * boundary, where the trace is gathered from the volume points, and point
+ * sets that do not, where it is evaluated from the coefficients):
+ *   GLL:   n = p + 2 Gauss-Lobatto-Legendre points per direction (default).
+ *   GAUSS: n = p + 2 Gauss-Legendre points per direction.  Exact for
+ *          polynomial integrands of degree 2p + 3 per direction (GLL:
+ *          2p + 1), so on trilinear elements the lambda term is integrated
+ *          exactly; on affine elements both give the same operator.
+ * The interface integrals keep the shared trace's GLL points (max p + 2 per
+ * direction) either way: under GAUSS each side's u and C.grad u there come
+ * from its coefficients (the trace stage), and the flux terms go back to the
+ * modes by the transposed evaluation.  GAUSS takes the geometry of deformed
+ * elements from their trilinear maps (no stored factors at the Gauss
+ * points) and affine elements' constants, whatever sipdg_set_geometry says.
+ * Requirements (EINVAL otherwise): a 3-D mesh, the shared-trace flux, and
+ * every order group on the gather-fold kernels (no element of order <= 6
+ * with a neighbour of order 7 or 8).  Switching to GAUSS selects the
+ * GATHER_FOLD structure; while set, sipdg_set_variant accepts only that one
+ * and sipdg_set_flux refuses the point-to-point flux.  sipdg_apply,
+ * sipdg_apply_stage, sipdg_apply_timed, sipdg_cg_solve and
+ * sipdg_gmres_solve use it (their Jacobi preconditioner stays the GLL
+ * operator's diagonal); sipdg_apply_transpose, sipdg_diagonal,
+ * sipdg_param_grad, sipdg_autotune, sipdg_quad_points and sipdg_load_vector
+ * return EINVAL.  Either basis.  No allocation (both table sets are built at
+ * create and by sipdg_set_basis). */
+#define SIPDG_POINTS_GLL 0
+#define SIPDG_POINTS_GAUSS 1
+int sipdg_set_points(sipdg_handle h, int points);
+int sipdg_get_points(sipdg_handle h, int *points);
+
 #define SIPDG_FLUX_SHARED 0
 #define SIPDG_FLUX_P2P 1
 int sipdg_set_flux(sipdg_handle h, int flux);

@@ -28,6 +28,7 @@ SIPDG_CG_F32_RU = 2
 GEOMETRY = {"stored": 0, "map": 1}
 FLUX = {"shared": 0, "p2p": 1}
 BASIS = {"legendre": 0, "modal": 1}
+POINTS = {"gll": 0, "gauss": 1}
 MAX_ORDER = 8
 VARIANTS = {"gather": 0, "two_stage": 1, "fused": 2, "gather_fold": 3, "gather_fold_fused": 4,
             "gather_fold_persistent": 5}
@@ -158,6 +159,8 @@ SIGNATURES = {
     "sipdg_set_flux": (_i, [_vp, _i]),
     "sipdg_set_basis": (_i, [_vp, _i]),
     "sipdg_get_basis": (_i, [_vp, ctypes.POINTER(_i)]),
+    "sipdg_set_points": (_i, [_vp, _i]),
+    "sipdg_get_points": (_i, [_vp, ctypes.POINTER(_i)]),
     "sipdg_get_flux": (_i, [_vp, ctypes.POINTER(_i)]),
     "sipdg_get_geometry": (_i, [_vp, ctypes.POINTER(_i)]),
     "sipdg_autotune": (_i, [_vp, _i, _vp, _vp]),

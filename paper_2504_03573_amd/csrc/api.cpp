@@ -155,10 +155,19 @@ static const R *emap_of(const sipdg_ctx *c) {
     if constexpr (sizeof(R) == 8) return (const R *)c->d_emap64;
     else return (const R *)c->d_emap32;
 }
+// the Gauss table set, in the apply's precision
+template <class R>
+static const R *tabgl_of(const sipdg_ctx *c) {
+    if constexpr (sizeof(R) == 8) return (const R *)c->d_tabgl64;
+    else return (const R *)c->d_tabgl32;
+}
 
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
                LaunchRec *rec) {
+    const bool gauss = c->points == SIPDG_POINTS_GAUSS;
+    if (gauss && (c->variant != SIPDG_VARIANT_GATHER_FOLD || c->flux != SIPDG_FLUX_SHARED))
+        return fail(SIPDG_EINVAL, "Gauss points run on the gather_fold structure with the shared-trace flux");
     if (c->flux == SIPDG_FLUX_P2P && c->variant != SIPDG_VARIANT_GATHER) {
         // point-to-point flux through the gather-fold apply: per order group a
         // trace launch (own pair, and the trace interpolated to each
@@ -337,6 +346,10 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 g3::Args A{A3.elems, A3.count, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, g.d_desc, g.d_fdesc, c->basis};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
+                // Gauss volume points: that table set (its trace tables are
+                // the GLL set's) and geometry from the maps or affine constants
+                if (gauss) D.tab = tabgl_of<R>(c);
+                const int def_mode = gauss ? 5 : (c->geo_map ? 4 : 1), aff_mode = gauss ? 6 : 3;
                 rec_mark(rec, stage, (int)gi, false, st);
                 hipError_t e = hipSuccess;
                 if (mode == 1 && g.split) {
@@ -359,15 +372,15 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                             hipStreamWaitEvent(c->aff_stream, c->aff_ev[0], 0) != hipSuccess)
                             return fail(SIPDG_EHIP, "event record / wait (affine fork)");
                     }
-                    e = launch_gfold3d<R>(g.P, 3, g.nfmax, Aa, D, side ? c->aff_stream : st);
-                    if (e == hipSuccess) e = launch_gfold3d<R>(g.P, c->geo_map ? 4 : 1, g.nfmax, Ad, D, st);
+                    e = launch_gfold3d<R>(g.P, aff_mode, g.nfmax, Aa, D, side ? c->aff_stream : st);
+                    if (e == hipSuccess) e = launch_gfold3d<R>(g.P, def_mode, g.nfmax, Ad, D, st);
                     if (side) {
                         if (hipEventRecord(c->aff_ev[1], c->aff_stream) != hipSuccess ||
                             hipStreamWaitEvent(st, c->aff_ev[1], 0) != hipSuccess)
                             return fail(SIPDG_EHIP, "event record / wait (affine join)");
                     }
                 } else {
-                    e = launch_gfold3d<R>(g.P, mode == 1 && c->geo_map ? 4 : mode, g.nfmax, A, D, st);
+                    e = launch_gfold3d<R>(g.P, mode == 1 ? def_mode : mode, g.nfmax, A, D, st);
                 }
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
@@ -467,7 +480,7 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
                     c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32,
                     c->d_tbuf_p2p, c->d_p2p_side, c->d_fgeo_p2p64, c->d_fgeo_p2p32,
-                    c->d_pfdesc_p2p};
+                    c->d_pfdesc_p2p, c->d_tabgl64, c->d_tabgl32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->d_pdesc) (void)hipFree(c->d_pdesc);
@@ -653,6 +666,10 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         TRY(upload(&c->d_tab64, tab));
         TRY(dalloc(&c->d_tab32, TAB_SIZE));
         TRYHIP(launch_cast_f32(c->d_tab64, c->d_tab32, TAB_SIZE, 0));
+        build_tables(tab.data(), 0, true);
+        TRY(upload(&c->d_tabgl64, tab));
+        TRY(dalloc(&c->d_tabgl32, TAB_SIZE));
+        TRYHIP(launch_cast_f32(c->d_tabgl64, c->d_tabgl32, TAB_SIZE, 0));
     }
     TRY(dalloc(&c->d_flag, 1));
     TRYHIP(hipMemset(c->d_flag, 0, sizeof(int)));
@@ -974,7 +991,9 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
                 const Group &g = h->groups[gi];
                 info[i].order = g.P;
                 info[i].elements = g.count;
-                info[i].alg_bytes = info[i].stage == 2 && h->flux == SIPDG_FLUX_SHARED ? g.alg_bytes[w] : 0.0;
+                info[i].alg_bytes = info[i].stage == 2 && h->flux == SIPDG_FLUX_SHARED && h->points == SIPDG_POINTS_GLL
+                                        ? g.alg_bytes[w]
+                                        : 0.0;
             } else {
                 // the persistent launch: every group of order <= 6 with traces <= 8 x 8
                 info[i].order = 0;
@@ -995,9 +1014,12 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
 static const char *P2P_ONLY_APPLY =
     "the point-to-point flux gives a nonsymmetric operator: only the apply calls and GMRES use it "
     "(set SIPDG_FLUX_SHARED for this call)";
+static const char *GAUSS_ONLY =
+    "Gauss volume points: only the apply calls, CG and GMRES use them (set SIPDG_POINTS_GLL for this call)";
 
 int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision, void *stream) {
     if (h && h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
+    if (h && h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     return sipdg_apply(h, g, xbar, precision, stream);
 }
 
@@ -1068,6 +1090,8 @@ int sipdg_set_flux(sipdg_handle h, int flux) {
     if (flux != SIPDG_FLUX_SHARED && flux != SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, "unknown flux");
     if (flux == SIPDG_FLUX_P2P) {
         if (h->dim != 3) return fail(SIPDG_EINVAL, "the point-to-point flux needs a 3-D mesh");
+        if (h->points == SIPDG_POINTS_GAUSS)
+            return fail(SIPDG_EINVAL, "the point-to-point flux takes GLL volume points (each side's own face points)");
         if (!h->d_tbuf_p2p) {
             int rc = build_p2p(h);
             if (rc) return rc;
@@ -1092,6 +1116,9 @@ int sipdg_set_basis(sipdg_handle h, int basis) {
     build_tables(tab.data(), basis);
     HIPCHK(hipMemcpy(h->d_tab64, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice));
     HIPCHK(launch_cast_f32(h->d_tab64, h->d_tab32, TAB_SIZE, 0));
+    build_tables(tab.data(), basis, true);
+    HIPCHK(hipMemcpy(h->d_tabgl64, tab.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice));
+    HIPCHK(launch_cast_f32(h->d_tabgl64, h->d_tabgl32, TAB_SIZE, 0));
     h->basis = basis;
     // the two-stage, fused and persistent structures evaluate Legendre
     // endpoint values in closed form; gather and gather-fold take either basis
@@ -1106,6 +1133,29 @@ int sipdg_set_basis(sipdg_handle h, int basis) {
     return SIPDG_OK;
 }
 
+int sipdg_set_points(sipdg_handle h, int points) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (points != SIPDG_POINTS_GLL && points != SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, "unknown point set");
+    if (points == SIPDG_POINTS_GAUSS) {
+        if (!h->gfold_ok) return fail(SIPDG_EINVAL, "Gauss volume points need a 3-D mesh");
+        if (h->flux != SIPDG_FLUX_SHARED)
+            return fail(SIPDG_EINVAL, "Gauss volume points take the shared-trace flux");
+        for (const Group &g : h->groups)
+            if (!gfold_group(g, false))
+                return fail(SIPDG_EINVAL, "Gauss volume points need every order group on the gather-fold kernels "
+                                          "(orders <= 6 with traces <= 8 x 8, orders 7 and 8 with traces <= 10 x 10)");
+        h->variant = SIPDG_VARIANT_GATHER_FOLD;
+    }
+    h->points = points;
+    return SIPDG_OK;
+}
+
+int sipdg_get_points(sipdg_handle h, int *points) {
+    if (!h || !points) return fail(SIPDG_EINVAL, "null argument");
+    *points = h->points;
+    return SIPDG_OK;
+}
+
 int sipdg_get_basis(sipdg_handle h, int *basis) {
     if (!h || !basis) return fail(SIPDG_EINVAL, "null argument");
     *basis = h->basis;
@@ -1115,6 +1165,7 @@ int sipdg_get_basis(sipdg_handle h, int *basis) {
 int sipdg_diagonal(sipdg_handle h, double *d, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
+    if (h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     if (h->ndof == 0) return SIPDG_OK;
     if (!d) return fail(SIPDG_EINVAL, "null argument");
     HIPCHK(hipMemcpyAsync(d, h->d_diag64, sizeof(double) * h->ndof, hipMemcpyDeviceToDevice, (hipStream_t)stream));
@@ -1167,6 +1218,7 @@ int sipdg_num_affine(sipdg_handle h, int64_t *n_affine) {
 
 int sipdg_quad_points(sipdg_handle h, double *xq, double *xb, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     if (h->ne == 0) return SIPDG_OK;
     if (!xq || (!xb && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
     HIPCHK(launch_points(h->dim, h->ne, h->d_corners, h->d_order, h->d_eface, h->d_qoff, h->d_boff,
@@ -1176,6 +1228,7 @@ int sipdg_quad_points(sipdg_handle h, double *xq, double *xb, void *stream) {
 
 int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *b, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     if (h->ndof == 0) return SIPDG_OK;
     if (!s || !b || (!g && h->nbq)) return fail(SIPDG_EINVAL, "null argument");
     for (const Group &gr : h->groups) {
@@ -1190,6 +1243,7 @@ int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *d
                      void *stream) {
     if (!h || !dsig) return fail(SIPDG_EINVAL, "null argument");
     if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
+    if (h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     hipStream_t st = (hipStream_t)stream;
     if (h->ne == 0) {   // empty mesh: every problem's penalty gradient is zero
         HIPCHK(hipMemsetAsync(dsig, 0, sizeof(double) * h->nprob, st));
@@ -1231,6 +1285,8 @@ int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *d
 
 int sipdg_set_variant(sipdg_handle h, int variant) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (h->points == SIPDG_POINTS_GAUSS && variant != SIPDG_VARIANT_GATHER_FOLD)
+        return fail(SIPDG_EINVAL, "Gauss volume points run on the gather_fold structure only");
     if (variant == SIPDG_VARIANT_GATHER) {
         h->variant = variant;
         return SIPDG_OK;
@@ -1272,6 +1328,7 @@ int sipdg_get_variant(sipdg_handle h, int *variant) {
 int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
+    if (h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     if (reps <= 0) reps = 20;
     hipStream_t st = (hipStream_t)stream;
     double *x = nullptr, *y = nullptr;

@@ -123,6 +123,10 @@ struct sipdg_ctx {
     double *d_corners = nullptr;
     double *d_tab64 = nullptr;
     float *d_tab32 = nullptr;
+    // the table set of Gauss volume points (X, W, B, D at the Gauss points)
+    double *d_tabgl64 = nullptr;
+    float *d_tabgl32 = nullptr;
+    int points = 0;         // SIPDG_POINTS_GLL or SIPDG_POINTS_GAUSS (volume quadrature)
     double *d_vgeo64 = nullptr, *d_fgeo64 = nullptr, *d_lam64 = nullptr, *d_tau64 = nullptr;
     float *d_vgeo32 = nullptr, *d_fgeo32 = nullptr, *d_lam32 = nullptr, *d_tau32 = nullptr;
     // per element [8]: G~ (00 01 02 11 12 22) and |J| of an affine (parallelepiped)

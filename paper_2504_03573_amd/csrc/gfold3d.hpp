@@ -178,9 +178,12 @@ __device__ __forceinline__ int btab_off(int m) {
     constexpr int N = P + 2;
     return 14 * (((m - 1) * m) / 2 - ((N - 1) * N) / 2);
 }
+// mode 3 (Gauss volume points): the point arrays, then the face terms of
+// every mode [NP^3] (no interpolation tables)
 template <int P>
 __host__ __device__ constexpr int lds_total(int mode) {
-    return Sz<P>::TOTAL + ((ITab<P>::SIZE + 3) & ~3) + (mode == 2 ? ((BTab<P>::SIZE + 3) & ~3) : 0);
+    return mode == 3 ? Sz<P>::TOTAL + (((P + 1) * (P + 1) * (P + 1) + 3) & ~3)
+                     : Sz<P>::TOTAL + ((ITab<P>::SIZE + 3) & ~3) + (mode == 2 ? ((BTab<P>::SIZE + 3) & ~3) : 0);
 }
 
 template <int P>
@@ -297,7 +300,8 @@ __device__ __forceinline__ FaceU<R> face_uniform(const MetaV<R> &m, int f) {
 // element's own face coordinates: the canonical index, a = w J_s, the
 // element's C along its (k, a, b) directions, and
 //   MODE 1: the element's own (u, g) = (ou, og) and the neighbour's
-//           (n0, n1) from the trace buffer,
+//           (n0, n1) from the trace buffer (MODE 3: the same, own values
+//           always from the buffer),
 //   MODE 2: the neighbour's C along its own (k, a, b) directions.
 template <class R>
 struct FaceD {
@@ -325,10 +329,10 @@ __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &
     d.Cb = Co[dir_b(k) * npf];
     if (MODE == 0) return d;
     d.aw = fg[d.qc];
-    if (MODE == 1) {
+    if (MODE == 1 || MODE == 3) {
         const R *__restrict__ tb = D.tbuf + u.to + d.qc;
         const int so = tb_side(u.slot);
-        if constexpr (!Sz<P>::OWN) {
+        if constexpr (!Sz<P>::OWN || MODE == 3) {
             d.ou = tb[so * 2 * npf];
             d.og = tb[so * 2 * npf + npf];
         }
@@ -673,6 +677,101 @@ __device__ __forceinline__ void face_pair_fused(const R *itl, const R *btl, cons
     lift2<R, P>(itl, fA.nf, fB.nf, sm, LA, LB);
 }
 
+// 1-D mode i and its derivative at s = -1 (side 0) or +1 (side 1) for the
+// basis of the handle: Legendre (P_i(+-1), P'_i(+-1)) or modified C0
+// (psi_0 = (1 - x)/2, psi_1 = (1 + x)/2, bubbles zero at both ends with
+// psi'_i(-1) = (-1)^i (i-1)/2, psi'_i(+1) = -(i-1)/2).
+template <class R>
+__device__ __forceinline__ void end_vd(int basis, int i, int s, R &v, R &d) {
+    if (basis == 0) {
+        v = end_val<R>(i, s);
+        d = end_der<R>(i, s);
+    } else if (i < 2) {
+        v = (i == s) ? R(1) : R(0);
+        d = i == 0 ? R(-0.5) : R(0.5);
+    } else {
+        const R h = R(0.5 * (i - 1));
+        v = R(0);
+        d = (s || (i & 1)) ? -h : h;
+    }
+}
+
+// Gauss volume points (apply MODE 3): the element boundary is not among the
+// volume points, so the faces' terms go to the modes directly.  For the two
+// faces normal to xi_k, lane (t1, t2) forms L = (F_v, F_g C_k, F_g C_a,
+// F_g C_b) at its trace point from both sides' (u, g) in the trace buffer;
+// the transpose of the trace evaluation (TraceIProduct on the trace's GLL
+// points, then the transpose of TracePhysEval's face-normal reduction) adds
+//   sum_t L0 phi_i + L1 d_k phi_i + L2 d_a phi_i + L3 d_b phi_i
+// to mode i = (i_k, i_a, i_b) of YF [NP^3].  Scratch LS: 14 W values.
+template <class R, int P>
+__device__ __forceinline__ void gauss_faces(const Args &A, const Data<R> &D, const MetaV<R> &meta, R *LS, R *YF) {
+    constexpr int NP = P + 1, WG = Geo<P>::W, SG = Geo<P>::S, NM = NP * NP * NP;
+    const int l = threadIdx.x, a = gx<P>(l), b = gy<P>(l);
+    for (int i = l; i < NM; i += WG) YF[i] = R(0);
+    R *SS = LS + 8 * WG;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        int nfs[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const FaceU<R> fu = face_uniform<R>(meta, 2 * k + s);
+            const FaceD<R> fd = load_face<R, P, 3>(D, fu, k);
+            R L[4];
+            flux_tb<R, P>(fu, fd, L);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) LS[(4 * s + f) * WG + l] = L[f];
+            nfs[s] = fu.nf;
+        }
+        __syncthreads();
+        // transposed contraction along b: lane (t1, i_b)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int nf = nfs[s];
+            if (a < nf && b < NP) {
+                const R *__restrict__ bf = D.tab + tab_off_BF(nf) + b;
+                const R *__restrict__ dbf = D.tab + tab_off_DBF(nf) + b;
+                const R *Lp = LS + 4 * s * WG + a;
+                R s0 = 0, s1 = 0, s2 = 0;
+                for (int t2 = 0; t2 < nf; ++t2) {
+                    const R bv = bf[t2 * S9];
+                    s0 += bv * Lp[SG * t2] + dbf[t2 * S9] * Lp[3 * WG + SG * t2];
+                    s1 += bv * Lp[WG + SG * t2];
+                    s2 += bv * Lp[2 * WG + SG * t2];
+                }
+                SS[3 * s * WG + l] = s0;
+                SS[(3 * s + 1) * WG + l] = s1;
+                SS[(3 * s + 2) * WG + l] = s2;
+            }
+        }
+        __syncthreads();
+        // transposed contraction along a, then the face-normal expansion:
+        // lane (i_a, i_b) owns the modes (*, i_a, i_b) of this direction
+        if (a < NP && b < NP) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int nf = nfs[s];
+                const R *__restrict__ bf = D.tab + tab_off_BF(nf) + a;
+                const R *__restrict__ dbf = D.tab + tab_off_DBF(nf) + a;
+                const R *Sp = SS + 3 * s * WG + SG * b;
+                R v0 = 0, v1 = 0;
+                for (int t1 = 0; t1 < nf; ++t1) {
+                    const R bv = bf[t1 * S9];
+                    v0 += bv * Sp[t1] + dbf[t1 * S9] * Sp[2 * WG + t1];
+                    v1 += bv * Sp[WG + t1];
+                }
+#pragma unroll
+                for (int ik = 0; ik < NP; ++ik) {
+                    R ev, ed;
+                    end_vd<R>(A.basis, ik, s, ev, ed);
+                    YF[mode_rt(NP, k, a, b, ik)] += ev * v0 + ed * v1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Where the apply takes an element's geometric factors from (a launch of
 // one kind covers elements of one kind).
 enum : int {
@@ -786,6 +885,10 @@ __device__ __forceinline__ void pointwise(const Data<R> &D, const ElemDesc &ed, 
 //   trace buffer written by the trace stage (k3t_elem); orders 6 and 8 take
 //   their own (u, g) from their face values instead.
 // MODE 2 (apply, fused): y = A x with the neighbours' traces evaluated here.
+// MODE 3 (apply, Gauss volume points): the volume terms at the element's
+//   Gauss points (tables and factors of that set: D.tab is the Gauss table
+//   set, GEO the map or affine constants), the faces' terms from the trace
+//   buffer lifted to the modes (gauss_faces), added at the write of y.
 // One element: descriptor blk of A.desc / A.fdesc, LDS at smem_raw.
 template <class R, int P, int MODE, int GEO = GEO_POINT>
 __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
@@ -807,11 +910,17 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     const MetaV<R> meta = load_meta<R, MODE>(A, D, blk);
     // interpolation tables of this order into LDS (read after several syncs)
     R *itl = SA + S::TOTAL;
+    if constexpr (MODE != 3) {
 #pragma unroll
-    for (int m = N + 1; m <= Geo<P>::NFMAX; ++m) {
-        const R *__restrict__ src = D.tab + tab_off_I(N, m);
-        for (int i = l; i < m * N; i += WG) itl[itab_off<P>(m) + i] = src[i];
+        for (int m = N + 1; m <= Geo<P>::NFMAX; ++m) {
+            const R *__restrict__ src = D.tab + tab_off_I(N, m);
+            for (int i = l; i < m * N; i += WG) itl[itab_off<P>(m) + i] = src[i];
+        }
     }
+    // Gauss volume points: the faces' terms of every mode first (the point
+    // arrays serve as scratch), kept after them
+    R *YF = SA + S::TOTAL;
+    if constexpr (MODE == 3) gauss_faces<R, P>(A, D, meta, SA, YF);
     // fused: the trace tables, and every neighbour's face-normal reduction
     // (their coefficient loads in flight together, during the volume work)
     R *btl = itl + ((ITab<P>::SIZE + 3) & ~3);
@@ -891,7 +1000,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     // apply kernels: the first faces' per-point data in flight during the line phases
     FaceU<R> fu0, fu1;
     FaceD<R> fd0, fd1;
-    {
+    if constexpr (MODE != 3) {
         fu0 = face_uniform<R>(meta, 0);
         fd0 = load_face<R, P, MODE>(D, fu0, 0);
         fu1 = face_uniform<R>(meta, 1);
@@ -981,7 +1090,9 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     __syncthreads();
 
 
-    if constexpr (MODE == 1) {
+    if constexpr (MODE == 3) {
+        if (col) pointwise<R, P, GEO>(D, ed, a, b, u, d0, d1, d2);
+    } else if constexpr (MODE == 1) {
     // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
     // in chunks, so that the factor loads of one chunk are in flight together
     if (col) pointwise<R, P, GEO>(D, ed, a, b, u, d0, d1, d2);
@@ -1217,6 +1328,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
             R s = 0;
 #pragma unroll
             for (int j = 0; j < N; ++j) s += Bt[j * NP + i] * v[j];
+            if constexpr (MODE == 3) s += YF[i + NP * (a + NP * b)];
             ye[i] = s;
         }
     }

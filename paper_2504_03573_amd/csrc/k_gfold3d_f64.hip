@@ -16,7 +16,7 @@ hipError_t gfold_p(int mode, int nfmax, const g3::Args &A, const g3::Data<double
     // the lane grid covers traces up to NFMAX x NFMAX points
     if (nfmax > g3::Geo<P>::NFMAX) return hipErrorInvalidValue;
     if (A.count <= 0) return hipSuccess;
-    const size_t lds = sizeof(double) * g3::lds_mode<P>(mode >= 3 ? 1 : mode);
+    const size_t lds = sizeof(double) * g3::lds_mode<P>(mode >= 5 ? 3 : (mode >= 3 ? 1 : mode));
     const dim3 blk(g3::Geo<P>::W);
     if (mode == 0 && A.side && A.basis) hipLaunchKernelGGL((g3::k3t<double, P, 1, true>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 0 && A.side) hipLaunchKernelGGL((g3::k3t<double, P, 0, true>), dim3(A.count), blk, lds, st, A, D);
@@ -25,6 +25,9 @@ hipError_t gfold_p(int mode, int nfmax, const g3::Args &A, const g3::Data<double
     else if (mode == 1) hipLaunchKernelGGL((g3::k3g<double, P, 1>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 3) hipLaunchKernelGGL((g3::k3g<double, P, 1, g3::GEO_AFFINE>), dim3(A.count), blk, lds, st, A, D);
     else if (mode == 4) hipLaunchKernelGGL((g3::k3g<double, P, 1, g3::GEO_MAP>), dim3(A.count), blk, lds, st, A, D);
+    // Gauss volume points: map geometry (5) or affine constants (6)
+    else if (mode == 5) hipLaunchKernelGGL((g3::k3g<double, P, 3, g3::GEO_MAP>), dim3(A.count), blk, lds, st, A, D);
+    else if (mode == 6) hipLaunchKernelGGL((g3::k3g<double, P, 3, g3::GEO_AFFINE>), dim3(A.count), blk, lds, st, A, D);
     else if (A.basis) return hipErrorInvalidValue;   // the fused kernel: Legendre endpoint values
     else if constexpr (P <= 6) hipLaunchKernelGGL((g3::k3g<double, P, 2>), dim3(A.count), blk, lds, st, A, D);
     else return hipErrorInvalidValue;   // the fused kernel covers orders <= 6

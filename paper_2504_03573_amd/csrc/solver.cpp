@@ -179,7 +179,7 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
     int *gpre = sizeof(R) == 8 ? &w->gpre64 : &w->gpre32;
     int *gop = sizeof(R) == 8 ? &w->gop64 : &w->gop32;
     const int pre = o.precond != 0;
-    const int opk = 4 * c->variant + 2 * c->basis + (c->geo_map ? 1 : 0);
+    const int opk = 32 * c->points + 4 * c->variant + 2 * c->basis + (c->geo_map ? 1 : 0);
     if (o.graph_k > 0 && maxit >= k && (*gexec == nullptr || *gk != k || *gpre != pre || *gop != opk)) {
         if (*gexec) {
             (void)hipGraphExecDestroy(*gexec);

@@ -2,7 +2,8 @@
 //
 // GLL nodes: the endpoints and the roots of P'_{n-1}, found by Newton's
 // method from the Chebyshev-Gauss-Lobatto points; weights
-// 2 / (n (n-1) P_{n-1}(x)^2).  Collocation derivative and interpolation use
+// 2 / (n (n-1) P_{n-1}(x)^2).  Gauss nodes: the roots of P_n by Newton's
+// method from the Chebyshev-Gauss points; weights 2 / ((1 - x^2) P'_n(x)^2).  Collocation derivative and interpolation use
 // the barycentric form of Lagrange interpolation (Berrut & Trefethen 2004).
 #include "tables.hpp"
 
@@ -54,6 +55,30 @@ void gll_nodes_weights(int n, double *x, double *w) {
     }
 }
 
+void gauss_nodes_weights(int n, double *x, double *w) {
+    double P[NMAX + 2], dP[NMAX + 2];
+    for (int j = 0; j < n; ++j) {
+        double t = -std::cos(M_PI * (j + 0.5) / n);
+        for (int it = 0; it < 100; ++it) {
+            legendre_with_derivs(n, t, P, dP);
+            const double dt = P[n] / dP[n];
+            t -= dt;
+            if (std::fabs(dt) < 1e-17) break;
+        }
+        x[j] = t;
+    }
+    for (int j = 0; j < n / 2; ++j) {  // exact symmetry
+        const double s = 0.5 * (x[n - 1 - j] - x[j]);
+        x[j] = -s;
+        x[n - 1 - j] = s;
+    }
+    if (n % 2) x[n / 2] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        legendre_with_derivs(n, x[j], P, dP);
+        w[j] = 2.0 / ((1.0 - x[j] * x[j]) * dP[n] * dP[n]);
+    }
+}
+
 static void bary_weights(int n, const double *x, double *lam) {
     for (int j = 0; j < n; ++j) {
         double p = 1.0;
@@ -81,11 +106,14 @@ static void legendre_to_modal(int p, const double *P, const double *dP, double *
     }
 }
 
-void build_tables(double *tab, int basis) {
+void build_tables(double *tab, int basis, bool gauss) {
     std::memset(tab, 0, sizeof(double) * TAB_SIZE);
-    double X[NMAX + 1][NMAX], W[NMAX + 1][NMAX];
+    // X: the volume points (GLL or Gauss); G: the GLL points of the traces
+    double X[NMAX + 1][NMAX], W[NMAX + 1][NMAX], G[NMAX + 1][NMAX], GW[NMAX + 1][NMAX];
     for (int n = NMIN; n <= NMAX; ++n) {
-        gll_nodes_weights(n, X[n], W[n]);
+        gll_nodes_weights(n, G[n], GW[n]);
+        if (gauss) gauss_nodes_weights(n, X[n], W[n]);
+        else gll_nodes_weights(n, X[n], W[n]);
         for (int j = 0; j < n; ++j) {
             tab[tab_off_X(n) + j] = X[n][j];
             tab[tab_off_W(n) + j] = W[n][j];
@@ -119,26 +147,30 @@ void build_tables(double *tab, int basis) {
             }
             D[i * n + i] = diag;
         }
+        // interpolation between GLL sets (the fold of the GLL volume points
+        // onto a finer trace; unused with Gauss volume points)
+        double lg[NMAX];
+        bary_weights(n, G[n], lg);
         for (int m = NMIN; m <= NMAX; ++m) {
             double *I = tab + tab_off_I(n, m);
             for (int t = 0; t < m; ++t) {
-                double y = X[m][t];
+                double y = G[m][t];
                 int hit = -1;
                 for (int j = 0; j < n; ++j)
-                    if (y == X[n][j]) hit = j;
+                    if (y == G[n][j]) hit = j;
                 if (hit >= 0) {
                     for (int j = 0; j < n; ++j) I[t * n + j] = (j == hit) ? 1.0 : 0.0;
                     continue;
                 }
                 double den = 0.0;
-                for (int j = 0; j < n; ++j) den += lam[j] / (y - X[n][j]);
-                for (int j = 0; j < n; ++j) I[t * n + j] = (lam[j] / (y - X[n][j])) / den;
+                for (int j = 0; j < n; ++j) den += lg[j] / (y - G[n][j]);
+                for (int j = 0; j < n; ++j) I[t * n + j] = (lg[j] / (y - G[n][j])) / den;
             }
         }
     }
     for (int m = NMIN; m <= NMAX; ++m) {
         for (int t = 0; t < m; ++t) {
-            legendre_with_derivs(PMAX, X[m][t], P, dP);
+            legendre_with_derivs(PMAX, G[m][t], P, dP);
             if (basis == 1) {
                 double M[PMAX + 2], dM[PMAX + 2];
                 legendre_to_modal(PMAX, P, dP, M, dM);

@@ -11,6 +11,9 @@
 //                     (gather + interpolate to the shared trace)
 //   BF(m)   [m][PMAX+1], DBF(m): modes and their derivatives at m GLL points
 //   X(n), W(n)        GLL nodes and weights
+// A second set for Gauss (Gauss-Legendre) volume points has X, W, B and D at
+// the n = P+2 Gauss points instead; I, BF and DBF (the shared trace stays on
+// its GLL points) are the same in both sets.
 #pragma once
 
 namespace sipdg {
@@ -45,10 +48,12 @@ constexpr int tab_off_W(int n) { return TAB_DBF_END + NPAIR * NMAX + (n - NMIN) 
 constexpr int TAB_SIZE = TAB_DBF_END + 2 * NPAIR * NMAX;
 
 // Host: fill a TAB_SIZE array (FP64) for the given modal basis (0 Legendre,
-// 1 modified C0; B, BF and DBF depend on it, the rest does not).
-void build_tables(double *tab, int basis = 0);
+// 1 modified C0; B, BF and DBF depend on it, the rest does not) and volume
+// point set (gauss: Gauss-Legendre instead of GLL for X, W, B and D).
+void build_tables(double *tab, int basis = 0, bool gauss = false);
 
 // Host helpers also used by the topology/validation code.
 void gll_nodes_weights(int n, double *x, double *w);
+void gauss_nodes_weights(int n, double *x, double *w);
 
 }  // namespace sipdg

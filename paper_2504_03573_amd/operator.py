@@ -199,7 +199,7 @@ class SipdgOperator:
     @property
     def basis(self) -> str:
         """Modal basis of the coefficients: "legendre" (orthogonal, the
-        default) or "modal" (modified C0; runs on the general kernels)."""
+        default) or "modal" (modified C0, Table 1)."""
         v = ctypes.c_int()
         C.check(self._lib.sipdg_get_basis(self._h, ctypes.byref(v)))
         return {b: a for a, b in C.BASIS.items()}[v.value]
@@ -207,6 +207,20 @@ class SipdgOperator:
     @basis.setter
     def basis(self, name: str):
         C.check(self._lib.sipdg_set_basis(self._h, C.BASIS[name]))
+
+    @property
+    def points(self) -> str:
+        """Volume quadrature points: "gll" (p + 2 Gauss-Lobatto points per
+        direction, the default) or "gauss" (p + 2 Gauss points; the faces
+        keep the shared trace's GLL points, each side's trace evaluated from
+        its coefficients).  Under "gauss": apply, cg_solve and gmres_solve."""
+        v = ctypes.c_int()
+        C.check(self._lib.sipdg_get_points(self._h, ctypes.byref(v)))
+        return {b: a for a, b in C.POINTS.items()}[v.value]
+
+    @points.setter
+    def points(self, name: str):
+        C.check(self._lib.sipdg_set_points(self._h, C.POINTS[name]))
 
     @property
     def flux(self) -> str:
