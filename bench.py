@@ -16,9 +16,12 @@ with deformed elements' geometric factors derived at every point from their
 trilinear maps instead of read from HBM (a variant of the method, reported
 beside the metric); `p2p` times the application with the point-to-point
 interpolation flux instead of the shared trace (the paper's alternative);
-`modal` times it in the modified C0 modal basis of Table 1.
+`modal` times it in the modified C0 modal basis of Table 1, and `gauss` with
+p+2 Gauss (Gauss-Legendre) volume points instead of GLL (the faces keep the
+shared trace's GLL points), with its FP64 PCG solve.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cg] [--no-cpu] [--no-map] [--no-p2p] [--no-modal]
+                    [--no-gauss]
 """
 
 from __future__ import annotations
@@ -194,6 +197,8 @@ def main():
                     help="kernel structure to use instead of the autotuner's choice (profiling runs)")
     ap.add_argument("--no-modal", action="store_true",
                     help="skip the apply in the modified C0 modal basis")
+    ap.add_argument("--no-gauss", action="store_true",
+                    help="skip the apply with Gauss volume points")
     ap.add_argument("--no-p2p", action="store_true",
                     help="skip the apply with the point-to-point interpolation flux")
     ap.add_argument("--no-map", action="store_true",
@@ -388,7 +393,7 @@ def main():
         op.flux = "shared"
     if not args.no_modal:
         # the modified C0 modal basis (Table 1 "Modal"): a congruent operator,
-        # run by the table-driven general kernels; reported beside the metric
+        # on the default gather-fold path; reported beside the metric
         keep = op.variant
         op.basis = "modal"
         for _ in range(args.warmup):
@@ -399,6 +404,32 @@ def main():
         out["modal"] = {"value": ndof / (ms_b * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms_b,
                         "fp32_value": ndof / (ms_b32 * 1e-3) / 1e9, "fp32_ms": ms_b32, "variant": op.variant}
         op.basis = "legendre"
+        op.variant = keep
+    if not args.no_gauss:
+        # Gauss volume points (point sets without the element boundary,
+        # Sec. 3.2): volume terms at p+2 Gauss points with geometry from the
+        # maps, faces from the trace stage lifted to the modes; another
+        # quadrature of the same form, reported beside the metric
+        keep = op.variant
+        op.points = "gauss"
+        for _ in range(args.warmup):
+            op.apply(x, out=y)
+            op.apply(x32, out=y32)
+        ms_g = time_events(lambda: op.apply(x, out=y), args.steps, stream)
+        ms_g32 = time_events(lambda: op.apply(x32, out=y32), args.steps, stream)
+        lg = op.apply_timed(x, y, reps=max(10, min(args.steps, 100)), stream=stream)
+        gs = {"value": ndof / (ms_g * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms_g,
+              "fp32_value": ndof / (ms_g32 * 1e-3) / 1e9, "fp32_ms": ms_g32,
+              "launches": [{"kernel": kernel_name("gather_fold", L["order"], 1) if L["stage"] == 1
+                            else "sipdg::g3::k3g<double, %d, 3, 2>" % L["order"], "ms": L["ms"]} for L in lg]}
+        if not args.no_cg:
+            op.cg_solve(bvec, tol=1e-10, mode="f64", maxit=50, raise_on_fail=False)
+            torch.cuda.synchronize()
+            _, info = op.cg_solve(bvec, tol=1e-10, mode="f64", maxit=100000, raise_on_fail=False)
+            gs["cg_f64"] = {"time_s": info["time_ms"] / 1e3, "iters": info["iters"],
+                            "converged": info["converged"], "rel_resid": info["rel_resid"]}
+        out["gauss"] = gs
+        op.points = "gll"
         op.variant = keep
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, x_np)

@@ -1,7 +1,8 @@
 """Parity at the workloads' full sizes, in the launch configuration the
 benchmark times: the whole 2-D 64^2 workload against the full oracle, and
 sampled element rows of the 3-D workloads (the oracle evaluates the rows of
-a random subset of elements one by one)."""
+a random subset of elements one by one), also with geometry from the maps,
+the point-to-point flux and Gauss volume points."""
 
 from __future__ import annotations
 
@@ -78,6 +79,16 @@ def test_workload_sampled_rows(env, k):
         assert np.linalg.norm(y32[rows] - yp_ref[rows]) <= 1e-5 * np.linalg.norm(yp_ref[rows])
     finally:
         op.flux = "shared"
+    # Gauss volume points against the oracle's Gauss operator, same rows
+    yg_ref = oracle.prepare(m, points="gl").apply(x, elems=elems)
+    op.points = "gauss"
+    try:
+        y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert np.linalg.norm(y[rows] - yg_ref[rows]) <= 1e-12 * np.linalg.norm(yg_ref[rows])
+        y32 = op.apply(torch.tensor(x, device="cuda", dtype=torch.float32)).double().cpu().numpy()
+        assert np.linalg.norm(y32[rows] - yg_ref[rows]) <= 1e-5 * np.linalg.norm(yg_ref[rows])
+    finally:
+        op.points = "gll"
     # properties at full size: symmetry and determinism
     rng2 = np.random.default_rng(20 + k)
     a = torch.tensor(rng2.standard_normal(op.n_dofs), device="cuda")
