@@ -178,11 +178,20 @@ __device__ __forceinline__ int btab_off(int m) {
     constexpr int N = P + 2;
     return 14 * (((m - 1) * m) / 2 - ((N - 1) * N) / 2);
 }
+// LDS copy of the trace tables for the Gauss apply: per trace size m = n ..
+// the largest trace, BF [m][NP] then DBF [m][NP].
+template <int P>
+struct GTab {
+    static constexpr int NP = P + 1, N = P + 2, M = Geo<P>::NFMAX;
+    static constexpr int off(int m) { return NP * ((m - 1) * m - (N - 1) * N); }
+    static constexpr int SIZE = off(M + 1);
+};
+
 // mode 3 (Gauss volume points): the point arrays, then the face terms of
-// every mode [NP^3] (no interpolation tables)
+// every mode [NP^3] and the trace tables (no interpolation tables)
 template <int P>
 __host__ __device__ constexpr int lds_total(int mode) {
-    return mode == 3 ? Sz<P>::TOTAL + (((P + 1) * (P + 1) * (P + 1) + 3) & ~3)
+    return mode == 3 ? Sz<P>::TOTAL + (((P + 1) * (P + 1) * (P + 1) + 3) & ~3) + GTab<P>::SIZE
                      : Sz<P>::TOTAL + ((ITab<P>::SIZE + 3) & ~3) + (mode == 2 ? ((BTab<P>::SIZE + 3) & ~3) : 0);
 }
 
@@ -703,25 +712,68 @@ __device__ __forceinline__ void end_vd(int basis, int i, int s, R &v, R &d) {
 // the transpose of the trace evaluation (TraceIProduct on the trace's GLL
 // points, then the transpose of TracePhysEval's face-normal reduction) adds
 //   sum_t L0 phi_i + L1 d_k phi_i + L2 d_a phi_i + L3 d_b phi_i
-// to mode i = (i_k, i_a, i_b) of YF [NP^3].  Scratch LS: 14 W values.
+// to mode i = (i_k, i_a, i_b) of YF [NP^3].  The trace tables go to GT in
+// LDS, loaded with the first direction's face data; each direction's face
+// data is loaded while the previous one is contracted.  Scratch LS: 14 W.
 template <class R, int P>
-__device__ __forceinline__ void gauss_faces(const Args &A, const Data<R> &D, const MetaV<R> &meta, R *LS, R *YF) {
-    constexpr int NP = P + 1, WG = Geo<P>::W, SG = Geo<P>::S, NM = NP * NP * NP;
+__device__ __forceinline__ void gauss_faces(const Args &A, const Data<R> &D, const MetaV<R> &meta, R *LS, R *YF,
+                                            R *GT) {
+    using G = GTab<P>;
+    constexpr int NP = P + 1, N = P + 2, WG = Geo<P>::W, SG = Geo<P>::S, NM = NP * NP * NP;
+    constexpr int HALF = G::SIZE / 2, BIT = (HALF + WG - 1) / WG;
     const int l = threadIdx.x, a = gx<P>(l), b = gy<P>(l);
+    // table entry i of the BF half: set m, row t, mode j (the DBF entry follows the set's BF rows)
+    R bv[2 * BIT];
+    int bo[BIT];
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+        const int i = l + it * WG;
+        int m = N, r = i;
+#pragma unroll
+        for (int mm = N; mm < G::M; ++mm)
+            if (r >= m * NP) {
+                r -= m * NP;
+                ++m;
+            }
+        const int t = r / NP, j = r - t * NP;
+        const bool ok = i < HALF;
+        bv[2 * it] = ok ? D.tab[tab_off_BF(m) + t * S9 + j] : R(0);
+        bv[2 * it + 1] = ok ? D.tab[tab_off_DBF(m) + t * S9 + j] : R(0);
+        bo[it] = ok ? G::off(m) + r + ((m * NP) << 16) : -1;
+    }
+    FaceU<R> fu[2];
+    FaceD<R> fd[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        fu[s] = face_uniform<R>(meta, s);
+        fd[s] = load_face<R, P, 3>(D, fu[s], 0);
+    }
     for (int i = l; i < NM; i += WG) YF[i] = R(0);
+#pragma unroll
+    for (int it = 0; it < BIT; ++it)
+        if (bo[it] >= 0) {
+            const int o = bo[it] & 0xffff, step = bo[it] >> 16;
+            GT[o] = bv[2 * it];
+            GT[o + step] = bv[2 * it + 1];
+        }
     R *SS = LS + 8 * WG;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         int nfs[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const FaceU<R> fu = face_uniform<R>(meta, 2 * k + s);
-            const FaceD<R> fd = load_face<R, P, 3>(D, fu, k);
             R L[4];
-            flux_tb<R, P>(fu, fd, L);
+            flux_tb<R, P>(fu[s], fd[s], L);
 #pragma unroll
             for (int f = 0; f < 4; ++f) LS[(4 * s + f) * WG + l] = L[f];
-            nfs[s] = fu.nf;
+            nfs[s] = fu[s].nf;
+        }
+        if (k < 2) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                fu[s] = face_uniform<R>(meta, 2 * (k + 1) + s);
+                fd[s] = load_face<R, P, 3>(D, fu[s], k + 1);
+            }
         }
         __syncthreads();
         // transposed contraction along b: lane (t1, i_b)
@@ -729,15 +781,14 @@ __device__ __forceinline__ void gauss_faces(const Args &A, const Data<R> &D, con
         for (int s = 0; s < 2; ++s) {
             const int nf = nfs[s];
             if (a < nf && b < NP) {
-                const R *__restrict__ bf = D.tab + tab_off_BF(nf) + b;
-                const R *__restrict__ dbf = D.tab + tab_off_DBF(nf) + b;
+                const R *bf = GT + G::off(nf) + b, *dbf = bf + nf * NP;
                 const R *Lp = LS + 4 * s * WG + a;
                 R s0 = 0, s1 = 0, s2 = 0;
                 for (int t2 = 0; t2 < nf; ++t2) {
-                    const R bv = bf[t2 * S9];
-                    s0 += bv * Lp[SG * t2] + dbf[t2 * S9] * Lp[3 * WG + SG * t2];
-                    s1 += bv * Lp[WG + SG * t2];
-                    s2 += bv * Lp[2 * WG + SG * t2];
+                    const R bt = bf[t2 * NP];
+                    s0 += bt * Lp[SG * t2] + dbf[t2 * NP] * Lp[3 * WG + SG * t2];
+                    s1 += bt * Lp[WG + SG * t2];
+                    s2 += bt * Lp[2 * WG + SG * t2];
                 }
                 SS[3 * s * WG + l] = s0;
                 SS[(3 * s + 1) * WG + l] = s1;
@@ -751,14 +802,13 @@ __device__ __forceinline__ void gauss_faces(const Args &A, const Data<R> &D, con
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int nf = nfs[s];
-                const R *__restrict__ bf = D.tab + tab_off_BF(nf) + a;
-                const R *__restrict__ dbf = D.tab + tab_off_DBF(nf) + a;
+                const R *bf = GT + G::off(nf) + a, *dbf = bf + nf * NP;
                 const R *Sp = SS + 3 * s * WG + SG * b;
                 R v0 = 0, v1 = 0;
                 for (int t1 = 0; t1 < nf; ++t1) {
-                    const R bv = bf[t1 * S9];
-                    v0 += bv * Sp[t1] + dbf[t1 * S9] * Sp[2 * WG + t1];
-                    v1 += bv * Sp[WG + t1];
+                    const R bt = bf[t1 * NP];
+                    v0 += bt * Sp[t1] + dbf[t1 * NP] * Sp[2 * WG + t1];
+                    v1 += bt * Sp[WG + t1];
                 }
 #pragma unroll
                 for (int ik = 0; ik < NP; ++ik) {
@@ -920,7 +970,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     // Gauss volume points: the faces' terms of every mode first (the point
     // arrays serve as scratch), kept after them
     R *YF = SA + S::TOTAL;
-    if constexpr (MODE == 3) gauss_faces<R, P>(A, D, meta, SA, YF);
+    if constexpr (MODE == 3) gauss_faces<R, P>(A, D, meta, SA, YF, YF + ((NP * NP * NP + 3) & ~3));
     // fused: the trace tables, and every neighbour's face-normal reduction
     // (their coefficient loads in flight together, during the volume work)
     R *btl = itl + ((ITab<P>::SIZE + 3) & ~3);
