@@ -266,9 +266,9 @@ int sipdg_get_basis(sipdg_handle h, int *basis);
  * with a neighbour of order 7 or 8).  Switching to GAUSS selects the
  * GATHER_FOLD structure; while set, sipdg_set_variant accepts only that one
  * and sipdg_set_flux refuses the point-to-point flux.  sipdg_apply,
- * sipdg_apply_stage, sipdg_apply_timed, sipdg_cg_solve and
- * sipdg_gmres_solve use it (their Jacobi preconditioner stays the GLL
- * operator's diagonal); sipdg_apply_transpose, sipdg_diagonal,
+ * sipdg_apply_stage, sipdg_apply_timed, sipdg_apply_transpose (the operator
+ * stays symmetric), sipdg_cg_solve and sipdg_gmres_solve use it (the solvers'
+ * Jacobi preconditioner stays the GLL operator's diagonal); sipdg_diagonal,
  * sipdg_param_grad, sipdg_autotune, sipdg_quad_points and sipdg_load_vector
  * return EINVAL.  Either basis.  No allocation (both table sets are built at
  * create and by sipdg_set_basis). */

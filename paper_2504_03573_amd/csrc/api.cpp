@@ -1015,11 +1015,12 @@ static const char *P2P_ONLY_APPLY =
     "the point-to-point flux gives a nonsymmetric operator: only the apply calls and GMRES use it "
     "(set SIPDG_FLUX_SHARED for this call)";
 static const char *GAUSS_ONLY =
-    "Gauss volume points: only the apply calls, CG and GMRES use them (set SIPDG_POINTS_GLL for this call)";
+    "Gauss volume points: only the apply calls (transpose included), CG and GMRES use them "
+    "(set SIPDG_POINTS_GLL for this call)";
 
 int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision, void *stream) {
+    // the shared-trace operator is symmetric on either point set
     if (h && h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
-    if (h && h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     return sipdg_apply(h, g, xbar, precision, stream);
 }
 

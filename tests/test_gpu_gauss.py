@@ -1,8 +1,9 @@
 """Gauss (Gauss-Legendre) volume points through the C ABI against the oracle's
 Gauss operator (pinned in test_oracle_gauss.py): FP64 within 1e-12 and FP32
 within 1e-5 (relative 2-norm), both bases; affine meshes give the GLL
-operator; switching back restores the GLL apply bit for bit; CG and GMRES
-solve the oracle's Gauss system; the calls that assume GLL points refuse."""
+operator; the operator is symmetric; switching back restores the GLL apply
+bit for bit; CG and GMRES solve the oracle's Gauss system; the calls that
+assume GLL points refuse."""
 
 from __future__ import annotations
 
@@ -92,6 +93,41 @@ def test_switch_back_bitwise(P):
     assert float((yg - y0).norm() / y0.norm()) >= 1e-9   # deformed: a different operator
 
 
+def test_symmetric_and_transpose(P):
+    """The Gauss operator stays symmetric (both quadratures are applied to the
+    symmetric form), so the transpose apply is the apply."""
+    m = synth.small_mesh(3, 3, ("random", 1, 5), seed=80, rotate=True, lam=0.8)
+    op = P.SipdgOperator(m)
+    op.points = "gauss"
+    rng = np.random.default_rng(81)
+    x = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda")
+    z = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda")
+    a, b = float(torch.dot(z, op.apply(x))), float(torch.dot(x, op.apply(z)))
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+    assert torch.equal(op.apply_transpose(x), op.apply(x))
+    # stage by stage equals the whole application
+    y = torch.empty_like(x)
+    op.apply_stage(x, 1, out=y)
+    op.apply_stage(x, 2, out=y)
+    assert torch.equal(y, op.apply(x))
+
+
+def test_lambda_and_penalty_changes(P, orc):
+    """set_lambda and set_penalty_scale act on the Gauss apply as on the GLL one."""
+    m = synth.small_mesh(3, 3, ("random", 2, 4), seed=82, rotate=True, lam=1.0)
+    op = P.SipdgOperator(m)
+    op.points = "gauss"
+    lam = np.random.default_rng(83).uniform(0.0, 5.0, m.n_elems)
+    op.set_lambda(torch.tensor(lam, device="cuda"))
+    op.set_penalty_scale(2.5)
+    m.lam = lam.copy()
+    m.sigma = 2.5
+    om = orc.prepare(m, points="gl")
+    x = synth.random_coefficients(m, 7106)
+    y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert rel(y, om.apply(x)) <= 1e-12
+
+
 def test_affine_equals_gll(P):
     """Both point sets integrate an affine element's terms exactly."""
     m = _affine(3, (1, 6), 72, rotate=True)
@@ -134,7 +170,7 @@ def test_refusals(P):
     op = P.SipdgOperator(m)
     x = torch.tensor(synth.random_coefficients(m, 7105), device="cuda")
     op.points = "gauss"
-    for call in (lambda: op.apply_transpose(x), op.diagonal, lambda: op.param_grad(x, x), op.autotune,
+    for call in (op.diagonal, lambda: op.param_grad(x, x), op.autotune,
                  lambda: setattr(op, "variant", "gather"), lambda: setattr(op, "flux", "p2p")):
         with pytest.raises(P.SipdgError):
             call()
