@@ -202,3 +202,25 @@ def test_batch_equals_singles(P):
         op.points = "gauss"
         yi = op.apply(x[off[i]:off[i + 1]].contiguous())
         assert float((y[off[i]:off[i + 1]] - yi).norm() / yi.norm()) <= 1e-14, i
+
+
+def test_autograd_wrt_inputs(P):
+    """Under Gauss points the autograd Functions differentiate with respect to
+    x and b (transpose apply, adjoint CG); lambda and sigma need the GLL
+    parameter-gradient kernels."""
+    from paper_2504_03573_amd import autograd as AG
+    m = synth.small_mesh(3, 3, ("random", 2, 4), seed=84, rotate=True, lam=1.0)
+    op = P.SipdgOperator(m)
+    op.points = "gauss"
+    rng = np.random.default_rng(85)
+    lam = torch.tensor(m.lam, device="cuda")
+    w = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda")
+    x = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda", requires_grad=True)
+    (w * AG.apply(op, x, lam, 1.0)).sum().backward()
+    assert torch.equal(x.grad, op.apply(w))
+    b = torch.tensor(rng.standard_normal(op.n_dofs), device="cuda", requires_grad=True)
+    (w * AG.solve(op, b, lam, 1.0)).sum().backward()
+    # db = A^{-1} w: A db = w
+    r = op.apply(b.grad) - w
+    assert float(r.norm() / w.norm()) <= 1e-9
+
