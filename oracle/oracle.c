@@ -610,7 +610,8 @@ int oracle_rhs(const omesh *m, const double *s_q, const double *g_b, double *b)
 
 /* Gradients of the bilinear form value aT A b with respect to lambda_e and
  * the penalty scale sigma:
- *   d/dlambda_e = (a, b)_{Omega_e}
+ *   d/dlambda_e = (a, b)_{Omega_e}, on the operator's volume quadrature
+ *                 (GLL or Gauss points: the one the lambda term of apply uses)
  *   d/dsigma    = sum_F (tau_F/sigma) ([[a]], [[b]])_F  (boundary: 2 a b). */
 int oracle_param_grad(const omesh *m, const double *av, const double *bv,
                       double *dlam, double *dsig_per_elem)
@@ -628,7 +629,8 @@ int oracle_param_grad(const omesh *m, const double *av, const double *bv,
 #pragma omp for schedule(dynamic, 4)
             for (long e = 0; e < m->ne; ++e) {
                 int p = m->order[e], n = p + 2, nm = ipow(p + 1, d), nq = ipow(n, d);
-                const double *gx = m->gll_x + n * OR_MAXN, *gw = m->gll_w + n * OR_MAXN;
+                /* the lambda term lives on the operator's own volume points */
+                const double *gx = m->vol_x + n * OR_MAXN, *gw = m->vol_w + n * OR_MAXN;
                 const double *ae = av + m->dof_off[e], *be = bv + m->dof_off[e];
                 double sl = 0.0;
                 for (int q = 0; q < nq; ++q) {

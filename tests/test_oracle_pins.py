@@ -204,18 +204,46 @@ def test_manufactured_convergence(oracle_lib):
         assert abs(slopes[-1] - (p + 1)) < 0.35, (p, errs, slopes)
 
 
-def test_param_grad_matches_finite_difference(oracle_lib):
+@pytest.mark.slow
+@pytest.mark.parametrize("p,Ns", [(2, (2, 4, 6)), (3, (2, 3, 4))])
+def test_manufactured_convergence_3d(oracle_lib, p, Ns):
+    """Hexahedra (perturbed trilinear elements): sin(pi x) sin(pi y) sin(pi z),
+    CG solve, L2 error slope close to p+1 over h = 1/N (Sec. 4.2, convergence
+    under p-refinement: around N_P = p + 1)."""
+    k = math.pi
+    lam = 1.0
+    ue = lambda X: np.sin(k * X[:, 0]) * np.sin(k * X[:, 1]) * np.sin(k * X[:, 2])
+    errs = []
+    for N in Ns:
+        m = synth.structured_mesh(3, N, 0.1, seed=1003, order=p, lam=lam)
+        om = oracle_lib.prepare(m)
+        b = om.rhs_from(lambda X: (lam + 3 * k * k) * ue(X), lambda X: np.zeros(len(X)))
+        x, it, rel = om.cg(b, tol=1e-12)
+        errs.append(om.l2_error(x, ue))
+    slopes = [math.log(errs[i] / errs[i + 1]) / math.log(Ns[i + 1] / Ns[i]) for i in range(len(Ns) - 1)]
+    assert abs(slopes[-1] - (p + 1)) < 0.35, (p, errs, slopes)
+    assert errs[-1] < errs[0]
+
+
+@pytest.mark.parametrize("basis,points", [("legendre", "gll"), ("legendre", "gl"), ("modal", "gll"),
+                                          ("modal", "gl")])
+def test_param_grad_matches_finite_difference(oracle_lib, basis, points):
     """d(a^T A b)/d lambda_e and d/d sigma: the operator is affine in both,
-    so a central difference of a^T A b is exact up to rounding."""
-    m = synth.small_mesh(3, 2, ("random", 1, 3), seed=51, lam=1.0, rotate=True)
+    so a central difference of a^T A b is exact up to rounding.  With Gauss
+    volume points the lambda derivative must come from the Gauss rule too:
+    on these deformed elements the two rules' mass terms differ by ~1e-4
+    relative, far above the tolerance."""
+    # 3^3 lattice: the centre element has all eight corners moved, so its
+    # |J| is not multilinear and the two volume rules differ on it
+    m = synth.small_mesh(3, 3, ("random", 1, 3), seed=51, lam=1.0, rotate=True)
     m.lam = np.random.default_rng(52).uniform(0.5, 2.0, m.n_elems)
-    om = oracle_lib.prepare(m)
+    om = oracle_lib.prepare(m, basis, points=points)
     rng = np.random.default_rng(53)
     a = rng.standard_normal(om.n_dofs)
     b = rng.standard_normal(om.n_dofs)
     dl, ds = om.param_grad(a, b)
     base = om.lam.copy()
-    for e in (0, 3, 7):
+    for e in (0, 3, 13):
         hstep = 1e-3
         om.lam[:] = base
         om.lam[e] += hstep
