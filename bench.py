@@ -119,6 +119,32 @@ def p2p_kernel_name(variant, order, stage):
     return "sipdg::g3::k3g<double, %d, 1, 0>" % order
 
 
+# CG vector traffic per iteration, in vector lengths: the dot p.q reads p and
+# q; the fused update reads x, r, p, q and the inverse diagonal and writes x,
+# r and z (with the two dot products r.z and r.r on the way); the direction
+# update reads z and p and writes p.  The operator application's own bytes
+# (p in, q out, factors) are its algorithmic bytes.
+CG_VECTOR_WORDS = 2 + 8 + 3
+
+
+def solve_record(info, ndof, apply_bytes, word):
+    """Time to tolerance and the throughput of one solve: DOF-iterations per
+    second (N_dof x iterations / time) and the HBM roofline fraction of an
+    average iteration (one application's algorithmic bytes plus the CG
+    vector traffic, over time per iteration).  For FP32 inside FP64
+    refinement the iterations are the inner FP32 ones, and time includes the
+    FP64 residual evaluations between them."""
+    t = info["time_ms"] * 1e-3
+    it = max(1, info["iters"])
+    per_iter = apply_bytes + CG_VECTOR_WORDS * word * ndof
+    return {"time_s": t, "iters": info["iters"], "outer_iters": info["outer_iters"],
+            "rel_resid": info["rel_resid"], "converged": info["converged"],
+            "ms_per_iter": info["time_ms"] / it,
+            "gdofs": ndof * it / t / 1e9 if t > 0 else None,
+            "bytes_per_iter": per_iter,
+            "roofline_frac": per_iter / (t / it) / 1e9 / HBM_PEAK_GBS if t > 0 else None}
+
+
 def time_events(fn, n, stream):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -173,6 +199,125 @@ def cpu_baseline(mesh, x, budget_s=12.0):
     }
 
 
+def _sines_source(dim, lam):
+    import torch
+
+    def src(X):
+        v = torch.ones(X.shape[0], dtype=torch.float64, device=X.device)
+        for a in range(dim):
+            v = v * torch.sin(math.pi * X[:, a])
+        return (lam + dim * math.pi ** 2) * v
+    return src
+
+
+def _zero(X):
+    import torch
+    return torch.zeros(X.shape[0], dtype=torch.float64, device=X.device)
+
+
+def bench_2d(args, stream):
+    """The two 2-D workloads: FP64 and FP32 application times (back to back)
+    and the FP64 PCG solve of the manufactured sin(pi x) sin(pi y) problem."""
+    import torch
+
+    import synth
+    from paper_2504_03573_amd import SipdgOperator, inspect_mesh
+    res = {}
+    for k in (1, 2):
+        m = synth.workload(k)
+        st = inspect_mesh(m)
+        op = SipdgOperator(m)
+        x = torch.tensor(synth.random_coefficients(m, 4000 + k), device="cuda")
+        y = torch.empty_like(x)
+        x32, y32 = x.float(), torch.empty_like(x, dtype=torch.float32)
+        for _ in range(args.warmup):
+            op.apply(x, out=y)
+            op.apply(x32, out=y32)
+        reps = max(args.steps, 100)
+        ms = time_events(lambda: op.apply(x, out=y), reps, stream)
+        ms32 = time_events(lambda: op.apply(x32, out=y32), reps, stream)
+        b = op.rhs(_sines_source(2, 1.0), _zero)
+        op.cg_solve(b, tol=1e-10, maxit=50, raise_on_fail=False)
+        torch.cuda.synchronize()
+        _, info = op.cg_solve(b, tol=1e-10, maxit=100000, raise_on_fail=False)
+        res["workload_%d" % k] = {
+            "workload": synth.WORKLOADS[k], "n_dofs": op.n_dofs,
+            "apply_us": ms * 1e3, "gdofs": op.n_dofs / (ms * 1e-3) / 1e9,
+            "apply_fp32_us": ms32 * 1e3, "gdofs_fp32": op.n_dofs / (ms32 * 1e-3) / 1e9,
+            "launches_per_apply": len(op.apply_timed(x, y, reps=5, stream=stream)),
+            "cg_f64": solve_record(info, op.n_dofs, algorithmic_bytes(st, 2, 8), 8),
+        }
+        op.close()
+    return res
+
+
+def bench_sweep(stream, reps=30):
+    """FP64 application throughput against problem size and order (the
+    paper's size study, Sec. 5.2): perturbed hex meshes N^3 with one order p
+    on every element (conforming), N chosen so that N_dof spans about 1e4 to
+    1e8; default kernel structure, no autotuning."""
+    import torch
+
+    import synth
+    from paper_2504_03573_amd import SipdgOperator
+    rows = []
+    for p in (3, 4, 5, 6):
+        for N in (4, 8, 16, 32, 48, 64):
+            ndof = N ** 3 * (p + 1) ** 3
+            if ndof > 1.1e8:
+                continue
+            m = synth.structured_mesh(3, N, 0.1, seed=7000 + N, order=p, lam=10.0)
+            op = SipdgOperator(m)
+            x = torch.randn(op.n_dofs, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(5):
+                op.apply(x, out=y)
+            ms = time_events(lambda: op.apply(x, out=y), reps, stream)
+            rows.append({"p": p, "N": N, "n_dofs": op.n_dofs, "ms": ms, "gdofs": op.n_dofs / (ms * 1e-3) / 1e9})
+            op.close()
+            del x, y
+            torch.cuda.empty_cache()
+    return rows
+
+
+def oracle_cg_times(gpu_2d):
+    """The oracle's Jacobi-PCG (plain FP64, OpenMP applications) to 1e-10 on
+    the 2-D workloads, and a bounded run of 10 iterations on the 3-D 24^3
+    workload (per-iteration time only: its full solve takes many minutes)."""
+    import numpy as np
+
+    import oracle
+    import synth
+    oracle.build(force=False)
+    res = {}
+    for k in (1, 2):
+        m = synth.workload(k)
+        om = oracle.prepare(m)
+        b = om.rhs_from(lambda X: (1.0 + 2 * math.pi ** 2) * np.sin(math.pi * X[:, 0]) * np.sin(math.pi * X[:, 1]),
+                        lambda X: np.zeros(len(X)))
+        t0 = time.perf_counter()
+        _, it, rel = om.cg(b, tol=1e-10)
+        dt = time.perf_counter() - t0
+        res["workload_%d" % k] = {"time_s": dt, "iters": it, "true_rel_resid": rel,
+                                  "gpu_time_s": (gpu_2d or {}).get("workload_%d" % k, {}).get("cg_f64", {}).get("time_s")}
+    m = synth.workload(5)
+    om = oracle.prepare(m)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(om.n_dofs)
+    t0 = time.perf_counter()
+    om.diagonal()
+    t_diag = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, it, _ = om.cg(b, tol=1e-30, maxit=10)
+    dt = time.perf_counter() - t0
+    res["workload_5"] = {"iters_timed": it, "time_s": dt, "diagonal_s": t_diag,
+                         "ms_per_iter": max(dt - 2 * t_diag, 0.0) / it * 1e3,
+                         "note": "bounded sample: 10 iterations of the oracle's PCG (its Jacobi diagonal and "
+                                 "final residual application taken out of the per-iteration time)"}
+    res["threads"] = oracle.num_threads()
+    return res
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -203,6 +348,10 @@ def main():
                     help="skip the apply with the point-to-point interpolation flux")
     ap.add_argument("--no-map", action="store_true",
                     help="skip the apply with geometry derived from the element maps")
+    ap.add_argument("--no-2d", action="store_true",
+                    help="skip the 2-D workloads (4^2 p=3 and 64^2 checkerboard 4/5)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the throughput sweep over problem size and order")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_hex32_p3to6.json"))
     args = ap.parse_args()
     if args.gpus != 1:
@@ -342,10 +491,7 @@ def main():
             op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=50, raise_on_fail=False)  # graph capture
             torch.cuda.synchronize()
             xs, info = op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=100000, raise_on_fail=False)
-            cg[mode] = {"time_s": info["time_ms"] / 1e3, "iters": info["iters"],
-                        "outer_iters": info["outer_iters"], "rel_resid": info["rel_resid"],
-                        "converged": info["converged"],
-                        "ms_per_iter": info["time_ms"] / max(1, info["iters"])}
+            cg[mode] = solve_record(info, ndof, b64 if mode == "f64" else b32, 8 if mode == "f64" else 4)
         out["cg"] = cg
     if not args.no_map:
         # the same operator with deformed elements' geometric factors derived at
@@ -369,8 +515,8 @@ def main():
                 op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=50, raise_on_fail=False)
                 torch.cuda.synchronize()
                 _, info = op.cg_solve(bvec, tol=1e-10, mode=mode, maxit=100000, raise_on_fail=False)
-                gm["cg_" + mode] = {"time_s": info["time_ms"] / 1e3, "iters": info["iters"],
-                                    "converged": info["converged"], "rel_resid": info["rel_resid"]}
+                gm["cg_" + mode] = solve_record(info, ndof, b64 if mode == "f64" else b32,
+                                                8 if mode == "f64" else 4)
         out["geometry_map"] = gm
         op.geometry = "stored"
         op.variant = keep
@@ -426,13 +572,18 @@ def main():
             op.cg_solve(bvec, tol=1e-10, mode="f64", maxit=50, raise_on_fail=False)
             torch.cuda.synchronize()
             _, info = op.cg_solve(bvec, tol=1e-10, mode="f64", maxit=100000, raise_on_fail=False)
-            gs["cg_f64"] = {"time_s": info["time_ms"] / 1e3, "iters": info["iters"],
-                            "converged": info["converged"], "rel_resid": info["rel_resid"]}
+            gs["cg_f64"] = solve_record(info, ndof, b64, 8)
         out["gauss"] = gs
         op.points = "gll"
         op.variant = keep
+    if not args.no_2d:
+        out["workloads_2d"] = bench_2d(args, stream)
+    if not args.no_sweep:
+        out["sweep"] = bench_sweep(stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, x_np)
+        if not args.no_cg:
+            out["cpu_baseline"]["cg"] = oracle_cg_times(out.get("workloads_2d"))
     print(json.dumps(out))
 
 

@@ -70,7 +70,9 @@ extern "C" {
 
 typedef struct sipdg_ctx *sipdg_handle;
 
-/* One mesh (one problem).  All arrays are host memory, read during create. */
+/* One mesh (one problem).  All arrays are host memory, read during create.
+ * A zero-initialised description plus the arrays and sizes is valid: basis 0
+ * is the Legendre basis and quad_extra 0 selects the default (2). */
 typedef struct {
     int dim;                       /* 2 or 3 */
     int64_t n_vertices;
@@ -81,6 +83,12 @@ typedef struct {
     const double *lambda;          /* [n_elems] Helmholtz coefficient per element */
     double h;                      /* nominal mesh size in tau_F (> 0) */
     double penalty_scale;          /* sigma in tau_F (> 0) */
+    int basis;                     /* SIPDG_BASIS_LEGENDRE (0) or SIPDG_BASIS_MODAL (1) (Table 1);
+                                      every problem of a batch the same (EINVAL otherwise) */
+    int quad_extra;                /* GLL points per direction n = p + quad_extra in the
+                                      element and n_F = p_F + quad_extra on a face
+                                      (Sec. 5.2 benchmark setting: 2).  0 or 2; any other value
+                                      returns EINVAL (the kernels are built for p + 2) */
 } sipdg_mesh_desc;
 
 /* Mesh statistics computed on the host without a device. */
@@ -94,10 +102,20 @@ typedef struct {
     int64_t elems_per_order[SIPDG_MAX_ORDER + 1];
 } sipdg_mesh_stats;
 
-/* Builds faces (matching by sorted corner ids, owner = lower element id,
- * orientation of the non-owner side), per-point geometric factors (FP64 and
- * an FP32 copy rounded once) and the Jacobi diagonal on the current device.
- * Synchronous.  Errors: EINVAL, EMESH, ENOMEM, EHIP. */
+/* Sets up the discrete SIPG operator of Sec. 2.2 (eq. IP, the primal form)
+ * on the mesh: faces matched by sorted corner ids (owner = lower element
+ * id, orientation of the non-owner side, Sec. 5.1), the shared trace of each
+ * interior face with max(p_L, p_R) + 2 GLL points per direction (Sec. 3.3),
+ * per-point geometric factors |J| J^-1 J^-T w and |J| w (Sec. 2.1; FP64 and an
+ * FP32 copy rounded once), per-trace-point a = w J_s and each side's
+ * s w (|J| J^-1 J^-T)[k], tau_F, and the Jacobi diagonal, on the current
+ * device.  Every device buffer the handle's calls use (trace buffers, CG
+ * work vectors, gradient scratch) is allocated here.  desc and its arrays
+ * are host memory read during the call; *out receives a handle owned by
+ * the caller until sipdg_destroy.  Synchronous.  Errors: EINVAL (null
+ * pointer, order outside [1, 8], dim, h, sigma, basis or quad_extra), EMESH
+ * (non-positive Jacobian, face shared by more than two elements, faces that
+ * do not match), ENOMEM, EHIP (no device). */
 int sipdg_create(const sipdg_mesh_desc *desc, sipdg_handle *out);
 
 /* Several independent problems in one handle: one vector holds them one
@@ -120,9 +138,15 @@ int sipdg_elem_offsets(sipdg_handle h, int64_t *off);
 /* host [n_problems+1] coefficient / element offsets of each problem */
 int sipdg_problem_offsets(sipdg_handle h, int64_t *dof_off, int64_t *elem_off);
 
-/* y = A x, async.  precision SIPDG_F64: x, y are double; SIPDG_F32: float,
- * computed with the FP32 copy of the geometric factors.  x and y must not
- * overlap.  Scratch (the trace buffer) is owned by the handle. */
+/* y = A x, the matrix-free application of the operator of Sec. 2.2 (eq. IP
+ * summed over elements and faces, i.e. the primal form), with the interface
+ * terms on the shared trace (Sec. 3.3) and the launch structure of Sec. 5.1
+ * (LhsEval: trace stage, then volume and flux stage).  x, y: device,
+ * [n_dofs] in the natural layout, owned by the caller; they must not
+ * overlap.  precision SIPDG_F64: double; SIPDG_F32: float, computed with the
+ * FP32 copy of the geometric factors.  Scratch (the trace buffer) is owned by
+ * the handle.  Async on stream.  Errors: EINVAL (null handle or vector), EHIP
+ * (launch failure). */
 int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *stream);
 
 /* One of the two stages of sipdg_apply, async (Sec. 5.1 splits LhsEval the
@@ -286,11 +310,48 @@ int sipdg_get_flux(sipdg_handle h, int *flux);
 #define SIPDG_GEOMETRY_MAP 1
 int sipdg_set_geometry(sipdg_handle h, int source);
 int sipdg_get_geometry(sipdg_handle h, int *source);
-/* Time one FP64 application with every allowed variant (reps each, HIP
- * events on the stream) and keep the fastest.  ms_out (host,
- * [SIPDG_NUM_VARIANTS], may be
- * NULL) receives the times (0 for variants not allowed).  Synchronous. */
-int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream);
+/* Autotuner (the per-order, compile-time specialised kernels of Sec. 5.1,
+ * chosen by measurement).  Times one FP64 application (reps each, HIP events
+ * on the stream, on the handle's CG work vectors: nothing is allocated) for
+ * every allowed kernel structure, the persistent structure's grid (blocks
+ * per compute unit), and for the gather-fold structure the tile shape of
+ * each order group (elements per workgroup and the register budget, see
+ * sipdg_tuning), and keeps the fastest.
+ * cache_path (host string, may be NULL): a JSON file of earlier results, one
+ * record per key "<mesh signature>-<library source hash>-<GPU arch>-<CUs>".
+ * A record with this handle's key is applied without timing; otherwise the
+ * result is added to the file (written to a temporary file, then renamed).
+ * ms_out (host, [SIPDG_NUM_VARIANTS], may be NULL) receives the times (from
+ * the record on a cache hit; 0 for structures not allowed).  Synchronous.
+ * Errors: EINVAL (point-to-point flux or Gauss points set), EHIP; a cache
+ * file that cannot be read or written is ignored (the tuning still runs). */
+int sipdg_autotune(sipdg_handle h, const char *cache_path, int reps, double *ms_out, void *stream);
+
+/* The handle's current tuning: kernel structure, persistent grid, whether it
+ * came from a cache file, the mesh signature (FNV-1a of dim, problems,
+ * orders, element corner ids and coordinates) and per order p the tile
+ * shape of the gather-fold apply launch: tile[p] = elements per workgroup
+ * (1 = one wavefront per element), budget[p] = waves per SIMD the register
+ * allocation targets. */
+typedef struct {
+    int variant;
+    int blocks_per_cu;
+    int from_cache;
+    uint64_t signature;
+    int tile[SIPDG_MAX_ORDER + 1];
+    int budget[SIPDG_MAX_ORDER + 1];
+} sipdg_tuning;
+int sipdg_get_tuning(sipdg_handle h, sipdg_tuning *t);
+
+/* Set the tile shape of order p's gather-fold apply launch by hand (what the
+ * autotuner chooses): tile = elements per workgroup, budget = waves per SIMD
+ * of the kernel's register allocation; (1, 2) is the one-wavefront-per-
+ * element kernel.  Tiles apply to the shared-trace apply of orders <= 5 with
+ * stored or map geometry (affine and Gauss-point launches keep one element
+ * per wavefront); results equal the one-element kernel's bit for bit.
+ * Errors: EINVAL (null handle, order outside [1, 8], a shape the library is
+ * not built with). */
+int sipdg_set_tile(sipdg_handle h, int order, int tile, int budget);
 
 /* xbar = A^T g, async.  The shared-trace SIPG operator is symmetric, so this
  * evaluates the same dataflow as sipdg_apply (Appendix A conditions hold by
@@ -301,10 +362,15 @@ int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precisi
 /* d = diag(A) in FP64 (device [n_dofs]), async. */
 int sipdg_diagonal(sipdg_handle h, double *d, void *stream);
 
-/* Gradients of the scalar a^T A b (a, b device FP64 [n_dofs]):
- * dlambda (device [n_elems]) = (a, b) on each element,
+/* Gradients of the scalar a^T A b with respect to the parameters (the
+ * differentiable operator, a project addition to the paper's method): the
+ * operator is affine in lambda and sigma, so
+ * dlambda (device [n_elems]) = (a, b) on each element, the lambda term of
+ * eq. IP integrated with the volume quadrature, and
  * dsigma (device [n_problems]) = sum_F tau_F/sigma ([[a]], [[b]])_F per problem
- * (boundary faces: 2 a b).  Async. */
+ * (boundary faces: 2 a b), the penalty term.  a, b: device FP64 [n_dofs].
+ * Scratch (a second trace buffer) comes from create.  Async.  Errors:
+ * EINVAL (null pointer, point-to-point flux or Gauss points set), EHIP. */
 int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *dlambda,
                      double *dsigma, void *stream);
 
@@ -330,9 +396,14 @@ int sipdg_num_affine(sipdg_handle h, int64_t *n_affine);
  * trace points (element by element, boundary faces in local face order
  * 2k+(s>0), points lexicographic in face coordinates).  Async. */
 int sipdg_quad_points(sipdg_handle h, double *xq, double *xb, void *stream);
-/* b = (phi_i, s) + boundary data terms -(g, grad phi_i . n) + 2 tau (g, phi_i),
+/* Right-hand side of the primal form (Sec. 2.2) with Dirichlet data by the
+ * mirrored exterior value u+ = -u- + 2 g (the boundary treatment of
+ * Sec. 2.2, penalty 2 tau_F):
+ * b = (phi_i, s) + the boundary data terms -(g, grad phi_i . n) + 2 tau (g, phi_i),
  * from source values s at the volume points and Dirichlet values g at the
- * boundary points (device FP64).  Async. */
+ * boundary points (device FP64, in sipdg_quad_points' order; g may be NULL
+ * when there are no boundary points).  b: device FP64 [n_dofs].  Async.
+ * Errors: EINVAL (null pointer, Gauss points set), EHIP. */
 int sipdg_load_vector(sipdg_handle h, const double *s, const double *g, double *b,
                       void *stream);
 
@@ -405,8 +476,15 @@ void sipdg_gmres_default_opts(sipdg_gmres_opts *o);
 int sipdg_gmres_solve(sipdg_handle h, const double *b, double *x, const sipdg_gmres_opts *opts,
                       sipdg_gmres_info *info, void *stream);
 
-/* Solve A x = b (device FP64 vectors).  Synchronous: returns when done.
- * Errors: ENOCONV, EBREAKDOWN, EINVAL, EHIP. */
+/* Solve A x = b by Jacobi-preconditioned conjugate gradients: the SIPG
+ * operator is symmetric and, for lambda > 0, positive definite, which is
+ * what the symmetric interior penalty is chosen for (Sec. 2.2); FP64, or
+ * FP32 inner solves inside FP64 iterative refinement (mode, a project
+ * addition).  b, x: device FP64 [n_dofs], owned by the caller (x is the
+ * initial guess when opts->x0_given).  CG iterations are captured in HIP
+ * graphs of opts->graph_k iterations.  Synchronous: returns when done.
+ * Errors: ENOCONV (maxit reached, info filled), EBREAKDOWN (p^T A p <= 0),
+ * EINVAL (null pointer, options, point-to-point flux set), EHIP. */
 int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_opts *opts,
                    sipdg_cg_info *info, void *stream);
 

@@ -47,6 +47,19 @@ class MeshDesc(ctypes.Structure):
         ("lambda_", ctypes.c_void_p),
         ("h", ctypes.c_double),
         ("penalty_scale", ctypes.c_double),
+        ("basis", ctypes.c_int),
+        ("quad_extra", ctypes.c_int),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("variant", ctypes.c_int),
+        ("blocks_per_cu", ctypes.c_int),
+        ("from_cache", ctypes.c_int),
+        ("signature", ctypes.c_uint64),
+        ("tile", ctypes.c_int * (MAX_ORDER + 1)),
+        ("budget", ctypes.c_int * (MAX_ORDER + 1)),
     ]
 
 
@@ -163,7 +176,9 @@ SIGNATURES = {
     "sipdg_get_points": (_i, [_vp, ctypes.POINTER(_i)]),
     "sipdg_get_flux": (_i, [_vp, ctypes.POINTER(_i)]),
     "sipdg_get_geometry": (_i, [_vp, ctypes.POINTER(_i)]),
-    "sipdg_autotune": (_i, [_vp, _i, _vp, _vp]),
+    "sipdg_autotune": (_i, [_vp, ctypes.c_char_p, _i, _vp, _vp]),
+    "sipdg_get_tuning": (_i, [_vp, ctypes.POINTER(Tuning)]),
+    "sipdg_set_tile": (_i, [_vp, _i, _i, _i]),
     "sipdg_last_error": (ctypes.c_char_p, []),
 }
 

@@ -21,15 +21,21 @@ from .operator import SipdgOperator
 
 
 def _set_params(op: SipdgOperator, lam: torch.Tensor, sigma: torch.Tensor):
+    """Give the handle (lambda, sigma) unless it already holds exactly these:
+    the cache key includes the handle's parameter generation, so a direct
+    op.set_lambda / op.set_penalty_scale in between is never missed."""
     lam = lam.detach().contiguous()
     if lam.dtype != torch.float64:
         raise TypeError("lambda must be float64")
     key = (lam.data_ptr(), getattr(lam, "_version", 0), float(sigma))
-    if getattr(op, "_param_key", None) != key or not torch.equal(getattr(op, "_lam_cache", lam), lam):
+    cached = getattr(op, "_param_key", None)
+    if (cached != key or getattr(op, "_param_gen_seen", None) != op.param_generation
+            or not torch.equal(getattr(op, "_lam_cache", lam), lam)):
         op.set_lambda(lam)
         op.set_penalty_scale(float(sigma))
         op._lam_cache = lam.clone()
         op._param_key = key
+        op._param_gen_seen = op.param_generation
 
 
 class SipdgApply(torch.autograd.Function):

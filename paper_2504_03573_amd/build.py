@@ -6,6 +6,7 @@ parallel and linked into one C-ABI library next to this file."""
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -31,9 +32,25 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src):
+def source_hash() -> str:
+    """SHA-256 prefix of the library's sources and public header: the
+    autotuner's cache keys include it, so a rebuilt library never takes a
+    tuning measured with other kernels."""
+    h = hashlib.sha256()
+    files = sorted(os.listdir(CSRC))
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    with open(os.path.join(INCLUDE, "sipdg.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, shash):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = ["hipcc"] + FLAGS + (["-x", "hip"] if src.endswith(".cpp") else []) + ["-c", src, "-o", obj]
+    cmd = (["hipcc"] + FLAGS + [f'-DSIPDG_SOURCE_HASH="{shash}"'] + (["-x", "hip"] if src.endswith(".cpp") else [])
+           + ["-c", src, "-o", obj])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{r.stderr}")
@@ -44,8 +61,9 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(8, os.cpu_count() or 4)
+    shash = source_hash()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, shash), srcs))
     tmp = LIB + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -3,15 +3,18 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "api_common.hpp"
 #include "sipdg.h"
+#include "solver.hpp"
 #include "topology.hpp"
 #include "fast3d.hpp"
 #include "gfold3d.hpp"
+#include "k_tile.hpp"
 #include <cstdlib>
 
 using namespace sipdg;
@@ -160,6 +163,18 @@ template <class R>
 static const R *tabgl_of(const sipdg_ctx *c) {
     if constexpr (sizeof(R) == 8) return (const R *)c->d_tabgl64;
     else return (const R *)c->d_tabgl32;
+}
+
+// The gather-fold apply launch of one order group (shared-trace flux): the
+// multi-element tile the handle is tuned to for stored-factor (mode 1) and
+// map-geometry (mode 4) launches of orders <= 5, else the one-element kernel.
+template <class R>
+static hipError_t launch_apply_group(const sipdg_ctx *c, int P, int mode, int nfmax, const g3::Args &A,
+                                     const g3::Data<R> &D, hipStream_t st) {
+    if ((mode == 1 || mode == 4) && P <= 5 && nfmax <= 8 && (c->tile[P] != 1 || c->budget[P] != 2))
+        return launch_gfold3d_tile<R>(P, mode == 4 ? g3::GEO_MAP : g3::GEO_POINT, c->tile[P], c->budget[P], A, D,
+                                      st);
+    return launch_gfold3d<R>(P, mode, nfmax, A, D, st);
 }
 
 template <class R>
@@ -373,14 +388,16 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                             return fail(SIPDG_EHIP, "event record / wait (affine fork)");
                     }
                     e = launch_gfold3d<R>(g.P, aff_mode, g.nfmax, Aa, D, side ? c->aff_stream : st);
-                    if (e == hipSuccess) e = launch_gfold3d<R>(g.P, def_mode, g.nfmax, Ad, D, st);
+                    if (e == hipSuccess) e = launch_apply_group<R>(c, g.P, def_mode, g.nfmax, Ad, D, st);
                     if (side) {
                         if (hipEventRecord(c->aff_ev[1], c->aff_stream) != hipSuccess ||
                             hipStreamWaitEvent(st, c->aff_ev[1], 0) != hipSuccess)
                             return fail(SIPDG_EHIP, "event record / wait (affine join)");
                     }
+                } else if (mode == 1) {
+                    e = launch_apply_group<R>(c, g.P, def_mode, g.nfmax, A, D, st);
                 } else {
-                    e = launch_gfold3d<R>(g.P, mode == 1 ? def_mode : mode, g.nfmax, A, D, st);
+                    e = launch_gfold3d<R>(g.P, mode, g.nfmax, A, D, st);
                 }
                 rec_mark(rec, stage, (int)gi, true, st);
                 if (e != hipSuccess)
@@ -500,6 +517,27 @@ static void free_ctx(sipdg_ctx *c) {
     }
     free_cg(c);
     delete c;
+}
+
+// FNV-1a over the mesh: dimension, problem count, element counts, orders,
+// corner coordinates (bit patterns) and face count.  Keys the autotuner's
+// cache: the same meshes give the same signature.
+static uint64_t mesh_signature(const Topology &T) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(&T.dim, sizeof(T.dim));
+    mix(&T.nprob, sizeof(T.nprob));
+    mix(T.prob_elem_off.data(), sizeof(int64_t) * T.prob_elem_off.size());
+    mix(T.order.data(), sizeof(int) * T.order.size());
+    mix(T.corners.data(), sizeof(double) * T.corners.size());
+    mix(&T.nfaces, sizeof(T.nfaces));
+    return h;
 }
 
 static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *out) {
@@ -835,13 +873,187 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
     TRY(dalloc(&c->d_diag64, T.ndof));
     TRY(dalloc(&c->d_dinv64, T.ndof));
     TRY(dalloc(&c->d_dinv32, T.ndof));
+    // every buffer a later call uses, now: the parameter gradients' second
+    // trace buffer and per-face / per-element partial sums, and the CG work
+    // vectors (also the autotuner's timing vectors)
+    TRY(dalloc(&c->d_tbuf2, std::max<int64_t>(1, c->tbuf_len)));
+    TRY(dalloc(&c->d_face_tmp, std::max<int64_t>(1, c->nfaces)));
+    TRY(dalloc(&c->d_elem_tmp, std::max<int64_t>(1, c->ne)));
+    TRY(alloc_cg(c));
+    c->signature = mesh_signature(T);
     TRY(refresh_diag(c, 0));
     TRYHIP(hipDeviceSynchronize());
+    if (descs[0].basis == SIPDG_BASIS_MODAL) TRY(sipdg_set_basis(c, SIPDG_BASIS_MODAL));
 #undef TRY
 #undef TRYHIP
     *out = c;
     return SIPDG_OK;
 }
+
+namespace {
+
+// ---------------------------------------------------------------- autotuner cache
+
+#ifndef SIPDG_SOURCE_HASH
+#define SIPDG_SOURCE_HASH "unversioned"
+#endif
+
+struct TuneRec {
+    int variant = 0, blocks_per_cu = 8;
+    int tile[SIPDG_MAX_ORDER + 1] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    int budget[SIPDG_MAX_ORDER + 1] = {2, 2, 2, 2, 2, 2, 2, 2, 2};
+    double ms[SIPDG_NUM_VARIANTS] = {0, 0, 0, 0, 0, 0};
+};
+
+std::string tune_key(const sipdg_ctx *h) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+        cus = prop.multiProcessorCount;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%016llx-%s-%s-%d", (unsigned long long)h->signature, SIPDG_SOURCE_HASH,
+                  arch.c_str(), cus);
+    return buf;
+}
+
+// integers / doubles of the JSON array after `name` on one record line
+template <class T>
+bool json_array(const std::string &line, const char *name, T *vals, int n) {
+    size_t p = line.find(name);
+    if (p == std::string::npos) return false;
+    p = line.find('[', p);
+    if (p == std::string::npos) return false;
+    const char *c = line.c_str() + p + 1;
+    for (int i = 0; i < n; ++i) {
+        char *end = nullptr;
+        const double v = std::strtod(c, &end);
+        if (end == c) return false;
+        vals[i] = (T)v;
+        c = end;
+        while (*c == ' ' || *c == ',') ++c;
+    }
+    return true;
+}
+
+bool json_int(const std::string &line, const char *name, int &v) {
+    size_t p = line.find(name);
+    if (p == std::string::npos) return false;
+    p = line.find(':', p);
+    if (p == std::string::npos) return false;
+    char *end = nullptr;
+    const long x = std::strtol(line.c_str() + p + 1, &end, 10);
+    if (end == line.c_str() + p + 1) return false;
+    v = (int)x;
+    return true;
+}
+
+// the cache file: a JSON object, one record per line
+//   "<key>": {"variant": V, "blocks_per_cu": B, "tile": [9], "budget": [9], "ms": [6]}
+std::vector<std::pair<std::string, std::string>> cache_records(const char *path) {
+    std::vector<std::pair<std::string, std::string>> out;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return out;
+    std::string line;
+    int ch;
+    auto flush = [&]() {
+        size_t a = line.find('"');
+        if (a != std::string::npos && line.find("\"variant\"") != std::string::npos) {
+            const size_t b = line.find('"', a + 1);
+            if (b != std::string::npos) {
+                std::string rec = line;
+                while (!rec.empty() && (rec.back() == ',' || rec.back() == ' ' || rec.back() == '\r')) rec.pop_back();
+                out.emplace_back(line.substr(a + 1, b - a - 1), rec);
+            }
+        }
+        line.clear();
+    };
+    while ((ch = std::fgetc(f)) != EOF) {
+        if (ch == '\n') flush();
+        else line.push_back((char)ch);
+    }
+    flush();
+    std::fclose(f);
+    return out;
+}
+
+bool cache_lookup(const char *path, const std::string &key, TuneRec &r) {
+    for (const auto &kv : cache_records(path)) {
+        if (kv.first != key) continue;
+        const std::string &l = kv.second;
+        TuneRec t;
+        if (!json_int(l, "\"variant\"", t.variant) || !json_int(l, "\"blocks_per_cu\"", t.blocks_per_cu) ||
+            !json_array(l, "\"tile\"", t.tile, SIPDG_MAX_ORDER + 1) ||
+            !json_array(l, "\"budget\"", t.budget, SIPDG_MAX_ORDER + 1) ||
+            !json_array(l, "\"ms\"", t.ms, SIPDG_NUM_VARIANTS))
+            return false;
+        r = t;
+        return true;
+    }
+    return false;
+}
+
+void cache_store(const char *path, const std::string &key, const TuneRec &r) {
+    auto recs = cache_records(path);
+    std::string line = "\"" + key + "\": {\"variant\": " + std::to_string(r.variant) +
+                       ", \"blocks_per_cu\": " + std::to_string(r.blocks_per_cu) + ", \"tile\": [";
+    for (int P = 0; P <= SIPDG_MAX_ORDER; ++P) line += (P ? ", " : "") + std::to_string(r.tile[P]);
+    line += "], \"budget\": [";
+    for (int P = 0; P <= SIPDG_MAX_ORDER; ++P) line += (P ? ", " : "") + std::to_string(r.budget[P]);
+    line += "], \"ms\": [";
+    for (int v = 0; v < SIPDG_NUM_VARIANTS; ++v) {
+        char b[64];
+        std::snprintf(b, sizeof(b), "%s%.6g", v ? ", " : "", r.ms[v]);
+        line += b;
+    }
+    line += "]}";
+    bool found = false;
+    for (auto &kv : recs)
+        if (kv.first == key) {
+            kv.second = line;
+            found = true;
+        }
+    if (!found) recs.emplace_back(key, line);
+    const std::string tmp = std::string(path) + ".tmp";
+    std::FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fputs("{\n", f);
+    for (size_t i = 0; i < recs.size(); ++i) {
+        std::fputs(recs[i].second.c_str(), f);
+        std::fputs(i + 1 < recs.size() ? ",\n" : "\n", f);
+    }
+    std::fputs("}\n", f);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) (void)std::rename(tmp.c_str(), path);
+    else (void)std::remove(tmp.c_str());
+}
+
+// a cached tuning, if this build and mesh allow every part of it
+int apply_tuning(sipdg_ctx *h, const TuneRec &r) {
+    for (int P = 1; P <= SIPDG_MAX_ORDER; ++P) {
+        bool ok = false;
+        for (const TileShape &ts : tile_shapes(P)) ok |= ts.tile == r.tile[P] && ts.budget == r.budget[P];
+        if (!ok) return SIPDG_EINVAL;
+    }
+    if (r.blocks_per_cu < 1 || r.blocks_per_cu > 64) return SIPDG_EINVAL;
+    const int keep = h->variant;
+    if (sipdg_set_variant(h, r.variant) != SIPDG_OK) {
+        h->variant = keep;
+        return SIPDG_EINVAL;
+    }
+    h->blocks_per_cu = r.blocks_per_cu;
+    for (int P = 0; P <= SIPDG_MAX_ORDER; ++P) {
+        h->tile[P] = r.tile[P];
+        h->budget[P] = r.budget[P];
+    }
+    return SIPDG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1251,11 +1463,6 @@ int sipdg_param_grad(sipdg_handle h, const double *a, const double *b, double *d
         return SIPDG_OK;
     }
     if (!a || !b || !dlam) return fail(SIPDG_EINVAL, "null argument");
-    if (!h->d_tbuf2) {
-        HIPCHK(hipMalloc((void **)&h->d_tbuf2, sizeof(double) * std::max<int64_t>(1, h->tbuf_len)));
-        HIPCHK(hipMalloc((void **)&h->d_face_tmp, sizeof(double) * std::max<int64_t>(1, h->nfaces)));
-        HIPCHK(hipMalloc((void **)&h->d_elem_tmp, sizeof(double) * std::max<int64_t>(1, h->ne)));
-    }
     // traces of a and b: the trace stage of the handle's kernel structure
     // (every structure but the fused ones has one), else the general kernels
     const bool fused = h->variant == SIPDG_VARIANT_FUSED || h->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED;
@@ -1326,50 +1533,99 @@ int sipdg_get_variant(sipdg_handle h, int *variant) {
     return SIPDG_OK;
 }
 
-int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
+int sipdg_autotune(sipdg_handle h, const char *cache_path, int reps, double *ms_out, void *stream) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (h->flux == SIPDG_FLUX_P2P) return fail(SIPDG_EINVAL, P2P_ONLY_APPLY);
     if (h->points == SIPDG_POINTS_GAUSS) return fail(SIPDG_EINVAL, GAUSS_ONLY);
     if (reps <= 0) reps = 20;
+    if (ms_out)
+        for (int v = 0; v < SIPDG_NUM_VARIANTS; ++v) ms_out[v] = 0.0;
+    const std::string key = tune_key(h);
+    TuneRec rec;
+    if (cache_path && cache_lookup(cache_path, key, rec) && apply_tuning(h, rec) == SIPDG_OK) {
+        h->tune_from_cache = true;
+        if (ms_out)
+            for (int v = 0; v < SIPDG_NUM_VARIANTS; ++v) ms_out[v] = rec.ms[v];
+        return SIPDG_OK;
+    }
+    h->tune_from_cache = false;
     hipStream_t st = (hipStream_t)stream;
+    // timing vectors: two of the CG work vectors (allocated at create)
     double *x = nullptr, *y = nullptr;
-    HIPCHK(hipMalloc((void **)&x, sizeof(double) * std::max<int64_t>(1, h->ndof)));
-    HIPCHK(hipMalloc((void **)&y, sizeof(double) * std::max<int64_t>(1, h->ndof)));
-    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * h->ndof, st));
+    cg_scratch(h, &x, &y);
+    if (!x || !y) return fail(SIPDG_EHIP, "internal: CG work vectors missing");
+    HIPCHK(vec_fill<double>(x, h->ndof, 0.0, st));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    auto time_apply = [&](double &ms_per) -> int {
+        int rc = SIPDG_OK;
+        for (int i = 0; i < 3 && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
+        if (rc == SIPDG_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(SIPDG_EHIP, "event record");
+        for (int i = 0; i < reps && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
+        if (rc == SIPDG_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            rc = fail(SIPDG_EHIP, "event sync");
+        float ms = 0.f;
+        if (rc == SIPDG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SIPDG_EHIP, "event time");
+        ms_per = ms / reps;
+        return rc;
+    };
     const int keep = h->variant;
     double best = 1e300;
     int best_v = keep;
     int rc = SIPDG_OK;
     for (int v = 0; v < SIPDG_NUM_VARIANTS && rc == SIPDG_OK; ++v) {
-        if (ms_out) ms_out[v] = 0.0;
+        rec.ms[v] = 0.0;
         const bool gf = v == SIPDG_VARIANT_GATHER_FOLD || v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT;
         if (gf ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)) continue;
         if (v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT && h->basis != SIPDG_BASIS_LEGENDRE) continue;
         h->variant = v;
-        // the persistent launch also tunes its shape: blocks per compute unit
-        const int shapes[] = {2, 4, 6, 8, 12, 16};
-        const int nshape = v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT ? 6 : 1;
         double vbest = 1e300;
-        int vshape = h->blocks_per_cu;
-        for (int si = 0; si < nshape && rc == SIPDG_OK; ++si) {
-            if (nshape > 1) h->blocks_per_cu = shapes[si];
-            for (int i = 0; i < 3 && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
-            if (hipEventRecord(e0, st) != hipSuccess) rc = fail(SIPDG_EHIP, "event record");
-            for (int i = 0; i < reps && rc == SIPDG_OK; ++i) rc = apply_impl<double>(h, x, y, h->d_tbuf, nullptr, st);
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-                rc = fail(SIPDG_EHIP, "event sync");
-            float ms = 0.f;
-            if (rc == SIPDG_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms / reps < vbest) {
-                vbest = ms / reps;
-                vshape = h->blocks_per_cu;
+        if (v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT) {
+            // the persistent launch's shape: blocks per compute unit
+            const int shapes[] = {2, 4, 6, 8, 12, 16};
+            int vshape = h->blocks_per_cu;
+            for (int si = 0; si < 6 && rc == SIPDG_OK; ++si) {
+                h->blocks_per_cu = shapes[si];
+                double t = 0.0;
+                rc = time_apply(t);
+                if (rc == SIPDG_OK && t < vbest) {
+                    vbest = t;
+                    vshape = shapes[si];
+                }
             }
+            h->blocks_per_cu = vshape;
+        } else if (v == SIPDG_VARIANT_GATHER_FOLD) {
+            // tile shape of each order group's apply launch, one order at a
+            // time (the others fixed at their best so far)
+            rc = time_apply(vbest);
+            for (int P = 1; P <= SIPDG_MAX_ORDER && rc == SIPDG_OK; ++P) {
+                bool present = false;
+                for (const Group &g : h->groups) present |= g.P == P && g.count > 0;
+                if (!present) continue;
+                const int t0 = h->tile[P], b0 = h->budget[P];
+                int bt = t0, bb = b0;
+                for (const TileShape &ts : tile_shapes(P)) {
+                    if (ts.tile == t0 && ts.budget == b0) continue;
+                    h->tile[P] = ts.tile;
+                    h->budget[P] = ts.budget;
+                    double t = 0.0;
+                    rc = time_apply(t);
+                    if (rc != SIPDG_OK) break;
+                    if (t < vbest) {
+                        vbest = t;
+                        bt = ts.tile;
+                        bb = ts.budget;
+                    }
+                }
+                h->tile[P] = bt;
+                h->budget[P] = bb;
+            }
+        } else {
+            rc = time_apply(vbest);
         }
-        if (nshape > 1) h->blocks_per_cu = vshape;
         if (rc == SIPDG_OK && vbest < 1e300) {
-            if (ms_out) ms_out[v] = vbest;
+            rec.ms[v] = vbest;
             if (vbest < best) {
                 best = vbest;
                 best_v = v;
@@ -1379,9 +1635,44 @@ int sipdg_autotune(sipdg_handle h, int reps, double *ms_out, void *stream) {
     h->variant = rc == SIPDG_OK ? best_v : keep;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipFree(x);
-    (void)hipFree(y);
-    return rc;
+    if (rc) return rc;
+    if (ms_out)
+        for (int v = 0; v < SIPDG_NUM_VARIANTS; ++v) ms_out[v] = rec.ms[v];
+    if (cache_path) {
+        rec.variant = h->variant;
+        rec.blocks_per_cu = h->blocks_per_cu;
+        for (int P = 0; P <= SIPDG_MAX_ORDER; ++P) {
+            rec.tile[P] = h->tile[P];
+            rec.budget[P] = h->budget[P];
+        }
+        cache_store(cache_path, key, rec);
+    }
+    return SIPDG_OK;
+}
+
+int sipdg_set_tile(sipdg_handle h, int order, int tile, int budget) {
+    if (!h) return fail(SIPDG_EINVAL, "null handle");
+    if (order < 1 || order > SIPDG_MAX_ORDER) return fail(SIPDG_EINVAL, "order outside [1, 8]");
+    for (const TileShape &ts : tile_shapes(order))
+        if (ts.tile == tile && ts.budget == budget) {
+            h->tile[order] = tile;
+            h->budget[order] = budget;
+            return SIPDG_OK;
+        }
+    return fail(SIPDG_EINVAL, "tile shape not built for this order");
+}
+
+int sipdg_get_tuning(sipdg_handle h, sipdg_tuning *t) {
+    if (!h || !t) return fail(SIPDG_EINVAL, "null argument");
+    t->variant = h->variant;
+    t->blocks_per_cu = h->blocks_per_cu;
+    t->from_cache = h->tune_from_cache ? 1 : 0;
+    t->signature = h->signature;
+    for (int P = 0; P <= SIPDG_MAX_ORDER; ++P) {
+        t->tile[P] = h->tile[P];
+        t->budget[P] = h->budget[P];
+    }
+    return SIPDG_OK;
 }
 
 const char *sipdg_last_error(void) { return g_last_error.c_str(); }

@@ -30,5 +30,9 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
 
 int refresh_diag(sipdg_ctx *c, hipStream_t st);
 void free_cg(sipdg_ctx *c);
+// CG work vectors (FP64 and FP32) and reduction partials, allocated at create
+int alloc_cg(sipdg_ctx *c);
+// device pointers of two CG work vectors of n_dofs doubles (autotuner timing)
+void cg_scratch(sipdg_ctx *c, double **a, double **b);
 
 }  // namespace sipdg

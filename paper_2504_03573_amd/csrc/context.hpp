@@ -148,8 +148,8 @@ struct sipdg_ctx {
     float *d_fgeo_p2p32 = nullptr;
     double *d_tau0 = nullptr;
     double *d_tbuf = nullptr;              // FP64-sized; the FP32 path reuses it
-    double *d_tbuf2 = nullptr;             // second trace buffer (gradients), lazy
-    double *d_face_tmp = nullptr, *d_elem_tmp = nullptr;  // lazy
+    double *d_tbuf2 = nullptr;             // second trace buffer (gradients)
+    double *d_face_tmp = nullptr, *d_elem_tmp = nullptr;
     double *d_diag64 = nullptr, *d_dinv64 = nullptr;
     float *d_dinv32 = nullptr;
     std::vector<sipdg::Group> groups;
@@ -171,6 +171,12 @@ struct sipdg_ctx {
     int pcount = 0;
     int num_cu = 256;
     int blocks_per_cu = 8;            // persistent grid = num_cu * blocks_per_cu
+    uint64_t signature = 0;           // mesh signature (autotuner cache key)
+    bool tune_from_cache = false;     // the current tuning came from a cache file
+    // gather-fold apply tile shape per order: elements per workgroup, and the
+    // register budget (waves per SIMD) of the kernel instance
+    int tile[9] = {1, 1, 1, 1, 1, 1, 1, 1, 1};
+    int budget[9] = {2, 2, 2, 2, 2, 2, 2, 2, 2};
     bool fast_ok = false;   // 3-D with every order <= 6
     bool gfold_ok = false;  // 3-D: gather-fold (general kernels for groups <= 6 next to orders 7-8)
 };

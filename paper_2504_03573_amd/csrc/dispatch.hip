@@ -1,5 +1,6 @@
 // Dimension / order dispatch of the per-order kernels.
 #include "op_instances.hpp"
+#include "tile_shapes.hpp"
 
 namespace sipdg {
 
@@ -69,5 +70,14 @@ int elems_per_block(int dim, int P) {
     return 1;
 }
 #undef EPB_CASE
+
+std::vector<TileShape> tile_shapes(int P) {
+    std::vector<TileShape> v = {{1, 2}};   // one wavefront per element: the default kernel
+#define SIPDG_TILE_ENTRY(PP, EE, BB) \
+    if (P == PP) v.push_back({EE, BB});
+    SIPDG_TILE_SHAPES(SIPDG_TILE_ENTRY)
+#undef SIPDG_TILE_ENTRY
+    return v;
+}
 
 }  // namespace sipdg

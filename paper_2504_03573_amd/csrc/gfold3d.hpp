@@ -59,6 +59,14 @@ struct Geo {
     static constexpr int S = P <= 6 ? 8 : 10;       // lane stride of the 2-D grids
     static constexpr int NFMAX = P <= 6 ? 8 : 10;   // largest trace per direction
 };
+// Thread index in the lane grid of one element's face phase: the block's
+// thread in the one-element kernels, the lane in its wavefront in the
+// multi-element tiles (there each wavefront runs one element's faces at a
+// time).
+template <int P>
+__device__ __forceinline__ int flane() {
+    return Geo<P>::W == 64 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+}
 template <int P>
 __device__ __forceinline__ int gx(int l) { return l % Geo<P>::S; }
 template <int P>
@@ -327,7 +335,7 @@ __device__ __forceinline__ FaceD<R> load_face(const Data<R> &D, const FaceU<R> &
     FaceD<R> d;
     d.qc = 0;
     d.aw = d.Ck = d.Ca = d.Cb = d.n0 = d.n1 = d.n2 = d.ou = d.og = R(0);
-    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
+    const int l = flane<P>(), t1 = gx<P>(l), t2 = gy<P>(l);
     if (t1 >= u.nf || t2 >= u.nf) return d;
     const int npf = u.npf;
     d.qc = canon_index(u.o, u.nf, t1, t2);
@@ -373,7 +381,7 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
     constexpr int N = P + 2;
     const bool nA = nfA != N, nB = nfB != N;
     if (!nA && !nB) return;
-    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
+    const int l = flane<P>(), t1 = gx<P>(l), t2 = gy<P>(l);
     R *ISA = sm, *ITA = sm + 4 * WG, *ISB = sm + 8 * WG, *ITB = sm + 12 * WG;
     const R *IA = itl + itab_off<P>(nfA), *IB = itl + itab_off<P>(nfB);
     if (t1 < N && t2 < N) {
@@ -438,16 +446,20 @@ __device__ __forceinline__ void own_trace2(const R *itl, int nfA, int nfB, R *sm
 
 // Transposed interpolation of the lifted flux of the two faces of one
 // direction back to the element's face points (scratch: 1024 R at sm).
-template <class R, int P>
+// UNI: every thread of the block reaches every barrier (the wavefronts of a
+// multi-element tile lift different elements' faces side by side).  FSI: the
+// field stride of the half-lifted arrays (rows t2 < n only: S n suffices).
+template <class R, int P, bool UNI = false, int FSI = Geo<P>::W>
 __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R LA[4], R LB[4]) {
     constexpr int WG = Geo<P>::W, SG = Geo<P>::S;
     (void)WG;
     (void)SG;
     constexpr int N = P + 2;
+    static_assert(FSI >= SG * N, "half-lifted rows t2 < n must fit the field stride");
     const bool nA = nfA != N, nB = nfB != N;
-    if (!nA && !nB) return;
-    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
-    R *ITA = sm, *ISA = sm + 4 * WG, *ITB = sm + 8 * WG, *ISB = sm + 12 * WG;
+    if (!UNI && !nA && !nB) return;
+    const int l = flane<P>(), t1 = gx<P>(l), t2 = gy<P>(l);
+    R *ITA = sm, *ISA = sm + 4 * WG, *ITB = sm + 4 * WG + 4 * FSI, *ISB = sm + 8 * WG + 4 * FSI;
     const R *IA = itl + itab_off<P>(nfA), *IB = itl + itab_off<P>(nfB);
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
@@ -466,7 +478,7 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
             }
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ISA[f * WG + l] = c[f];
+        for (int f = 0; f < 4; ++f) ISA[f * FSI + l] = c[f];
     }
     if (nB && t1 < nfB && t2 < N) {
         R c[4] = {0, 0, 0, 0};
@@ -479,7 +491,7 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
             }
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) ISB[f * WG + l] = c[f];
+        for (int f = 0; f < 4; ++f) ISB[f * FSI + l] = c[f];
     }
     __syncthreads();
     if (nA) {
@@ -490,7 +502,7 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
                 if (t < nfA) {
                     const R w = IA[t * N + t1];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * WG + t + SG * t2];
+                    for (int f = 0; f < 4; ++f) c[f] += w * ISA[f * FSI + t + SG * t2];
                 }
             }
         }
@@ -505,7 +517,7 @@ __device__ __forceinline__ void lift2(const R *itl, int nfA, int nfB, R *sm, R L
                 if (t < nfB) {
                     const R w = IB[t * N + t1];
 #pragma unroll
-                    for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * WG + t + SG * t2];
+                    for (int f = 0; f < 4; ++f) c[f] += w * ISB[f * FSI + t + SG * t2];
                 }
             }
         }
@@ -533,7 +545,7 @@ __device__ __forceinline__ void own_from_stash(const R *OS, int f0, FaceD<R> &dA
 // terms L = (F_v, F_g C_k, F_g C_a, F_g C_b), not yet lifted.
 template <class R, int P>
 __device__ __forceinline__ void flux_tb(const FaceU<R> &fu, const FaceD<R> &fd, R L[4]) {
-    const int l = threadIdx.x, t1 = gx<P>(l), t2 = gy<P>(l);
+    const int l = flane<P>(), t1 = gx<P>(l), t2 = gy<P>(l);
     R Fv = 0, Fg = 0;
     if (t1 < fu.nf && t2 < fu.nf) {
         const R un = fu.slot == 2 ? -fd.ou : fd.n0;   // mirrored exterior state on the boundary

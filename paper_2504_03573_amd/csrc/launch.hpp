@@ -1,11 +1,22 @@
 // Host-side launchers (implemented next to their kernels).
 #pragma once
 
+#include <vector>
+
 #include "context.hpp"
 
 namespace sipdg {
 
 enum OpKind { OP_TRACE = 0, OP_APPLY = 1 };
+
+// Tile shapes of the gather-fold apply launch of one order group that the
+// library is built with: elements per workgroup and the register budget
+// (waves per SIMD the kernel instance is compiled for).  The first entry is
+// the default; the autotuner chooses among them.
+struct TileShape {
+    int tile, budget;
+};
+std::vector<TileShape> tile_shapes(int P);
 
 // Operator kernels for one order group.  tsz must be work_size(nfm).
 template <class R>

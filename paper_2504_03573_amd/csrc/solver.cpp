@@ -61,6 +61,8 @@ void free_cg(sipdg_ctx *c) {
 
 #define ALLOC(ptr, n) HIPCHK(hipMalloc((void **)&(ptr), sizeof(*(ptr)) * (size_t)std::max<int64_t>(1, (n))))
 
+static int ensure_cg32(sipdg_ctx *c);
+
 static int ensure_cg(sipdg_ctx *c) {
     if (c->cg) return SIPDG_OK;
     CgWork *w = new CgWork();
@@ -126,6 +128,17 @@ static int ensure_cg(sipdg_ctx *c) {
     ALLOC(w->d_preconv, np);
     ALLOC(w->d_ratio, np);
     return SIPDG_OK;
+}
+
+int alloc_cg(sipdg_ctx *c) {
+    int rc = ensure_cg(c);
+    if (rc) return rc;
+    return ensure_cg32(c);
+}
+
+void cg_scratch(sipdg_ctx *c, double **a, double **b) {
+    *a = c->cg ? c->cg->x64 : nullptr;
+    *b = c->cg ? c->cg->q64 : nullptr;
 }
 
 static int ensure_cg32(sipdg_ctx *c) {

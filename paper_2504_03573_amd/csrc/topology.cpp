@@ -108,6 +108,18 @@ int build_topology(int nprob, const sipdg_mesh_desc *descs, Topology &T, std::st
             err = "h and penalty_scale must be positive";
             return SIPDG_EINVAL;
         }
+        if (d.quad_extra != 0 && d.quad_extra != 2) {
+            err = "quad_extra must be 2 (p + 2 GLL points per direction) or 0 for that default";
+            return SIPDG_EINVAL;
+        }
+        if (d.basis != SIPDG_BASIS_LEGENDRE && d.basis != SIPDG_BASIS_MODAL) {
+            err = "unknown basis";
+            return SIPDG_EINVAL;
+        }
+        if (d.basis != descs[0].basis) {
+            err = "every problem of a batch must use the same basis";
+            return SIPDG_EINVAL;
+        }
         T.prob_elem_off[p + 1] = T.prob_elem_off[p] + d.n_elems;
         vert_base[p] = vbase;
         vbase += d.n_vertices;

@@ -27,7 +27,7 @@ def _ptr(t: torch.Tensor):
 class _Desc:
     """Keeps the host arrays of one mesh alive while the library reads them."""
 
-    def __init__(self, dim, coords, elem_vertices, order, lam, h, sigma):
+    def __init__(self, dim, coords, elem_vertices, order, lam, h, sigma, basis=0, quad_extra=2):
         self.coords = np.ascontiguousarray(coords, dtype=np.float64)
         self.ev = np.ascontiguousarray(elem_vertices, dtype=np.int64)
         self.order = np.ascontiguousarray(order, dtype=np.int32)
@@ -36,18 +36,18 @@ class _Desc:
             dim=int(dim), n_vertices=self.coords.shape[0], coords=self.coords.ctypes.data,
             n_elems=self.ev.shape[0], elem_vertices=self.ev.ctypes.data,
             order=self.order.ctypes.data, lambda_=self.lam.ctypes.data, h=float(h),
-            penalty_scale=float(sigma))
+            penalty_scale=float(sigma), basis=int(basis), quad_extra=int(quad_extra))
 
 
-def _desc_from(mesh) -> _Desc:
+def _desc_from(mesh, basis: str = "legendre", quad_extra: int = 2) -> _Desc:
     return _Desc(mesh.dim, mesh.coords, mesh.elem_vertices, mesh.order, mesh.lam, mesh.h,
-                 getattr(mesh, "sigma", 1.0))
+                 getattr(mesh, "sigma", 1.0), C.BASIS[basis], quad_extra)
 
 
-def inspect_mesh(mesh) -> dict:
+def inspect_mesh(mesh, basis: str = "legendre", quad_extra: int = 2) -> dict:
     """Host-only statistics (face counts, orientations); needs no device."""
     lib = C.load()
-    d = _desc_from(mesh)
+    d = _desc_from(mesh, basis, quad_extra)
     st = C.MeshStats()
     C.check(lib.sipdg_mesh_inspect(ctypes.byref(d.desc), ctypes.byref(st)))
     return {
@@ -63,10 +63,10 @@ def inspect_mesh(mesh) -> dict:
 
 
 class SipdgOperator:
-    def __init__(self, mesh=None, _handle=None, _descs=None):
+    def __init__(self, mesh=None, basis: str = "legendre", quad_extra: int = 2, _handle=None, _descs=None):
         self._lib = C.load()
         if _handle is None:
-            d = _desc_from(mesh)
+            d = _desc_from(mesh, basis, quad_extra)
             h = ctypes.c_void_p()
             C.check(self._lib.sipdg_create(ctypes.byref(d.desc), ctypes.byref(h)))
             _handle = h
@@ -97,9 +97,9 @@ class SipdgOperator:
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
-    def batch(cls, meshes):
+    def batch(cls, meshes, basis: str = "legendre"):
         lib = C.load()
-        descs = [_desc_from(m) for m in meshes]
+        descs = [_desc_from(m, basis) for m in meshes]
         arr = (C.MeshDesc * len(descs))(*[d.desc for d in descs])
         h = ctypes.c_void_p()
         C.check(lib.sipdg_create_batch(len(descs), arr, ctypes.byref(h)))
@@ -235,11 +235,26 @@ class SipdgOperator:
     def flux(self, name: str):
         C.check(self._lib.sipdg_set_flux(self._h, C.FLUX[name]))
 
-    def autotune(self, reps: int = 20, stream=None) -> dict:
-        """Time every allowed kernel structure and keep the fastest."""
+    def autotune(self, reps: int = 20, cache_path: str | None = None, stream=None) -> dict:
+        """Time every allowed kernel structure (and the tile shape of each
+        order group's apply launch) and keep the fastest; with ``cache_path``
+        a JSON file of earlier results is consulted first and updated."""
         ms = (ctypes.c_double * len(C.VARIANTS))()
-        C.check(self._lib.sipdg_autotune(self._h, int(reps), ms, _stream_ptr(stream)))
+        cp = None if cache_path is None else str(cache_path).encode()
+        C.check(self._lib.sipdg_autotune(self._h, cp, int(reps), ms, _stream_ptr(stream)))
         return {name: ms[i] for name, i in C.VARIANTS.items() if ms[i] > 0}
+
+    def set_tile(self, order: int, tile: int, budget: int):
+        """Tile shape of one order's gather-fold apply launch (elements per
+        workgroup, register budget in waves per SIMD); (1, 2) is the default."""
+        C.check(self._lib.sipdg_set_tile(self._h, int(order), int(tile), int(budget)))
+
+    def tuning(self) -> dict:
+        t = C.Tuning()
+        C.check(self._lib.sipdg_get_tuning(self._h, ctypes.byref(t)))
+        names = {b: a for a, b in C.VARIANTS.items()}
+        return {"variant": names[t.variant], "blocks_per_cu": t.blocks_per_cu, "from_cache": bool(t.from_cache),
+                "signature": "%016x" % t.signature, "tile": list(t.tile), "budget": list(t.budget)}
 
     def diagonal(self, stream=None) -> torch.Tensor:
         d = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
@@ -255,11 +270,18 @@ class SipdgOperator:
                                            _stream_ptr(stream)))
         return dl, ds
 
+    # Every change of lambda or sigma bumps ``param_generation``, so a cache of
+    # the parameters the handle holds (the autograd Functions keep one) can
+    # tell that they were set from elsewhere.
+    param_generation = 0
+
     def set_lambda(self, lam: torch.Tensor, stream=None):
         self._vec(lam, torch.float64, n=self.n_elems, name="lambda")
+        self.param_generation += 1
         C.check(self._lib.sipdg_set_lambda(self._h, _ptr(lam), _stream_ptr(stream)))
 
     def set_penalty_scale(self, sigma: float, problem: int = -1):
+        self.param_generation += 1
         C.check(self._lib.sipdg_set_penalty_scale(self._h, int(problem), float(sigma)))
 
     def quad_points(self, stream=None):

@@ -120,3 +120,63 @@ def test_cg_default_opts_layout(capi):
     assert o.inner_tol == 1e-4 and o.precond == 1 and o.graph_k == 10 and o.max_outer == 50
     assert o.checkpoint_every == 0 and o.x0_given == 0 and o.ru_delta == 0.1
     assert capi.SIPDG_CG_F32_RU == 2
+
+
+def test_quad_extra_and_basis_fields(capi):
+    """quad_extra: 2 (p + 2 GLL points, what the kernels are built for) or 0
+    for that default; anything else is EINVAL.  basis: 0 or 1."""
+    from paper_2504_03573_amd import inspect_mesh
+    m = synth.small_mesh(3, 2, ("random", 1, 4), seed=2)
+    ref = inspect_mesh(m)
+    assert inspect_mesh(m, quad_extra=0) == ref
+    assert inspect_mesh(m, quad_extra=2) == ref
+    assert inspect_mesh(m, basis="modal") == ref
+    for q in (-1, 1, 3, 4):
+        with pytest.raises(capi.SipdgError) as ei:
+            inspect_mesh(m, quad_extra=q)
+        assert ei.value.code == -1
+    d = capi.MeshDesc()
+    from paper_2504_03573_amd.operator import _desc_from
+    keep = _desc_from(m)
+    d = keep.desc
+    d.basis = 2
+    st = capi.MeshStats()
+    assert capi.load().sipdg_mesh_inspect(ctypes.byref(d), ctypes.byref(st)) == -1
+
+
+def test_struct_layouts_match_header(capi, tmp_path):
+    """The ctypes mirrors of the ABI structs have the C compiler's sizes and
+    field offsets (a C program built against include/sipdg.h prints them)."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "sipdg.h"
+int main(void) {
+    printf("%zu %zu %zu %zu\n", sizeof(sipdg_mesh_desc), offsetof(sipdg_mesh_desc, penalty_scale),
+           offsetof(sipdg_mesh_desc, basis), offsetof(sipdg_mesh_desc, quad_extra));
+    printf("%zu %zu %zu %zu\n", sizeof(sipdg_tuning), offsetof(sipdg_tuning, signature),
+           offsetof(sipdg_tuning, tile), offsetof(sipdg_tuning, budget));
+    printf("%zu %zu %zu\n", sizeof(sipdg_cg_opts), offsetof(sipdg_cg_opts, checkpoint),
+           offsetof(sipdg_cg_opts, ru_delta));
+    printf("%zu %zu\n", sizeof(sipdg_launch_info), offsetof(sipdg_launch_info, alg_bytes));
+    return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    rows = [list(map(int, r.split())) for r in subprocess.check_output([str(exe)]).decode().split("\n") if r]
+    M, T, O, L = capi.MeshDesc, capi.Tuning, capi.CgOpts, capi.LaunchInfo
+    assert rows[0] == [ctypes.sizeof(M), M.penalty_scale.offset, M.basis.offset, M.quad_extra.offset]
+    assert rows[1] == [ctypes.sizeof(T), T.signature.offset, T.tile.offset, T.budget.offset]
+    assert rows[2] == [ctypes.sizeof(O), O.checkpoint.offset, O.ru_delta.offset]
+    assert rows[3] == [ctypes.sizeof(L), L.alg_bytes.offset]
+
+
+def test_tuning_calls_reject_null(capi):
+    lib = capi.load()
+    ms = (ctypes.c_double * 6)()
+    assert lib.sipdg_autotune(None, b"/nonexistent/cache.json", 5, ms, None) == -1
+    t = capi.Tuning()
+    assert lib.sipdg_get_tuning(None, ctypes.byref(t)) == -1

@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests.parity import rel, rel2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -74,8 +75,6 @@ def _n_affine_direct(mesh):
     return int((dev <= 1e-10 * size).sum())
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -163,7 +162,7 @@ def test_cg_and_param_grad(case):
     # back inside the graph) against plain launches, replayed several times
     xg, info_g = op.cg_solve(b, tol=1e-10, graph_k=0)
     x0, info0 = op.cg_solve(b, tol=1e-10, graph_k=5)
-    assert info0["converged"] and rel(x0.cpu().numpy(), xg.cpu().numpy()) <= 1e-8
+    assert info0["converged"] and rel2(x0.cpu().numpy(), xg.cpu().numpy()) <= 1e-8
     for _ in range(2):
         xh, info_h = op.cg_solve(b, tol=1e-10, graph_k=5)
         assert info_h["iters"] == info0["iters"] and torch.equal(xh, x0)

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests.parity import rel, rel2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -31,8 +32,6 @@ def orc():
     return oracle
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def _affine(N, orders, seed, deform=0.0, rotate=False, lam=2.0):
@@ -154,7 +153,7 @@ def test_solvers(P, orc):
         print(f"cg {mode}: {info}")
         assert info["converged"]
         assert np.linalg.norm(b - om.apply(xs)) <= 1e-9 * np.linalg.norm(b)
-        assert rel(xs, x_true) <= 1e-6
+        assert rel2(xs, x_true) <= 1e-6
     # the graph cache follows the point set: a GLL solve after the Gauss ones
     op.points = "gll"
     xs2, _ = op.cg_solve(bt, tol=1e-10)
@@ -162,7 +161,7 @@ def test_solvers(P, orc):
     op.points = "gauss"
     xg, info = op.gmres_solve(bt, tol=1e-10, restart=30)
     assert info["converged"]
-    assert rel(xg.cpu().numpy(), x_true) <= 1e-6
+    assert rel2(xg.cpu().numpy(), x_true) <= 1e-6
 
 
 def test_refusals(P):

@@ -67,3 +67,38 @@ def test_apply_timed(P, variant):
             assert torch.equal(y, y_ref)
         else:
             assert torch.allclose(y.double(), y_ref, rtol=0, atol=1e-5 * float(y_ref.abs().max()))
+
+
+def test_autotune_cache_round_trip(P, tmp_path):
+    """The autotuner writes its result to the JSON cache (key: mesh signature,
+    library source hash, GPU); a second handle on the same mesh takes the
+    cached tuning without timing; a different mesh adds a second record; the
+    applies agree bitwise whichever structure was kept."""
+    import json
+    print("[autotune cache]", flush=True)
+    path = tmp_path / "tune.json"
+    m = synth.workload(3, N=6)
+    op1 = P.SipdgOperator(m)
+    ms1 = op1.autotune(3, cache_path=path)
+    t1 = op1.tuning()
+    assert not t1["from_cache"] and ms1[t1["variant"]] == min(ms1.values())
+    rec = json.load(open(path))
+    assert len(rec) == 1
+    key = next(iter(rec))
+    assert key.startswith(t1["signature"])
+    assert rec[key]["variant"] == P._capi.VARIANTS[t1["variant"]]
+    op2 = P.SipdgOperator(m)
+    ms2 = op2.autotune(3, cache_path=path)
+    t2 = op2.tuning()
+    assert t2["from_cache"] and t2["variant"] == t1["variant"] and t2["tile"] == t1["tile"]
+    assert t2["budget"] == t1["budget"] and t2["signature"] == t1["signature"]
+    assert ms2 == pytest.approx(ms1, rel=1e-5)
+    x = torch.tensor(synth.random_coefficients(m, 4007), device="cuda")
+    assert torch.equal(op1.apply(x), op2.apply(x))
+    # another mesh: another key, the first record kept
+    m3 = synth.workload(5, N=4)
+    op3 = P.SipdgOperator(m3)
+    op3.autotune(3, cache_path=path)
+    assert op3.tuning()["signature"] != t1["signature"]
+    rec = json.load(open(path))
+    assert len(rec) == 2 and key in rec

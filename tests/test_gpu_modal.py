@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests.parity import rel, rel2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -38,8 +39,6 @@ CASES = {
 }
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 @pytest.fixture(scope="module", params=list(CASES))
