@@ -149,6 +149,24 @@ int sipdg_problem_offsets(sipdg_handle h, int64_t *dof_off, int64_t *elem_off);
  * (launch failure). */
 int sipdg_apply(sipdg_handle h, const void *x, void *y, int precision, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): y = A x
+ * exactly as sipdg_apply (same kernels, same results bit for bit), but the
+ * trace buffer between the two stages is a fixed device array of
+ * SIPDG_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, held until
+ * the process ends, its address looked up at sipdg_create) instead of the
+ * handle's buffer.  The call itself allocates nothing and enqueues only
+ * kernel launches on stream (async).  Every call on one GPU shares that
+ * array and leaves its contents behind (no call needs it cleared): calls on
+ * one GPU that overlap in time, from any handle or stream, race and give
+ * wrong results; serialise them.  Errors: EINVAL (null handle or vector,
+ * x == y, precision, point-to-point flux set, or a trace buffer of
+ * 4 (n_interior_trace_points) + 2 (n_boundary_trace_points) values at this
+ * precision larger than the scratch), EHIP (launch failure, no scratch
+ * address for the handle's device). */
+#define SIPDG_NOALLOC_SCRATCH_BYTES (160ll << 20)
+int sipdg_apply_noalloc(sipdg_handle h, const void *x, void *y, int precision, void *stream);
+
 /* One of the two stages of sipdg_apply, async (Sec. 5.1 splits LhsEval the
  * same way, with the trace exchange between the two parts):
  *   stage 1: trace values (u and w J_s n.grad u, owner point order) of every

@@ -20,6 +20,7 @@ ERRORS = {
     -5: "SIPDG_ENOCONV",
     -6: "SIPDG_EBREAKDOWN",
 }
+SIPDG_NOALLOC_SCRATCH_BYTES = 160 << 20
 SIPDG_F64 = 0
 SIPDG_F32 = 1
 SIPDG_CG_F64 = 0
@@ -151,6 +152,7 @@ SIGNATURES = {
     "sipdg_elem_offsets": (_i, [_vp, _vp]),
     "sipdg_problem_offsets": (_i, [_vp, _vp, _vp]),
     "sipdg_apply": (_i, [_vp, _vp, _vp, _i, _vp]),
+    "sipdg_apply_noalloc": (_i, [_vp, _vp, _vp, _i, _vp]),
     "sipdg_apply_transpose": (_i, [_vp, _vp, _vp, _i, _vp]),
     "sipdg_apply_stage": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "sipdg_apply_timed": (_i, [_vp, _vp, _vp, _i, _i, ctypes.POINTER(LaunchInfo), _i, ctypes.POINTER(_i), _vp]),

@@ -880,6 +880,8 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
     TRY(dalloc(&c->d_face_tmp, std::max<int64_t>(1, c->nfaces)));
     TRY(dalloc(&c->d_elem_tmp, std::max<int64_t>(1, c->ne)));
     TRY(alloc_cg(c));
+    // the allocation-free apply's scratch address on this device
+    TRY(noalloc_setup(c->device));
     c->signature = mesh_signature(T);
     TRY(refresh_diag(c, 0));
     TRYHIP(hipDeviceSynchronize());

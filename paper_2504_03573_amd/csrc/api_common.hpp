@@ -34,5 +34,8 @@ void free_cg(sipdg_ctx *c);
 int alloc_cg(sipdg_ctx *c);
 // device pointers of two CG work vectors of n_dofs doubles (autotuner timing)
 void cg_scratch(sipdg_ctx *c, double **a, double **b);
+// device address of the allocation-free apply's scratch array on `device`
+// (the current device), looked up once per device
+int noalloc_setup(int device);
 
 }  // namespace sipdg

@@ -135,6 +135,18 @@ class SipdgOperator:
         C.check(self._lib.sipdg_apply(self._h, _ptr(x), _ptr(y), prec, _stream_ptr(stream)))
         return y
 
+    def apply_noalloc(self, x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """y = A x through sipdg_apply_noalloc: the trace buffer is the
+        library's fixed per-GPU scratch array, so the call allocates nothing
+        (``out`` must be given).  Calls on one GPU must not overlap."""
+        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        if prec is None:
+            raise TypeError("x must be float64 or float32")
+        self._vec(x, x.dtype, name="x")
+        self._vec(out, x.dtype, name="out")
+        C.check(self._lib.sipdg_apply_noalloc(self._h, _ptr(x), _ptr(out), prec, _stream_ptr(stream)))
+        return out
+
     def apply_stage(self, x: torch.Tensor, stage: int, out: torch.Tensor | None = None, stream=None):
         """Stage 1 (trace values into the handle's buffer) or stage 2 (fluxes,
         volume terms, inner products into ``out``) of one application."""
