@@ -91,12 +91,18 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def kernel_name(variant, order, stage=2, geo_map=False):
-    """Kernel symbol (as rocprofv3 prints it, FP64) of one launch."""
+def kernel_name(variant, order, stage=2, geo_map=False, tuning=None):
+    """Kernel symbol (as rocprofv3 prints it, FP64) of one launch; tuning (the
+    handle's tile shapes) names the multi-element tile kernel of an order
+    group tuned to one."""
     if variant == "gather_fold":
         if stage == 1:
             return ("sipdg::g3::k3t_all<double, 0, false>" if order == 0
                     else "sipdg::g3::k3t<double, %d, 0, false>" % order)
+        if tuning and 1 <= order <= 5 and (tuning["tile"][order], tuning["budget"][order]) != (1, 2):
+            e, bud = tuning["tile"][order], tuning["budget"][order]
+            nw = (e * (order + 2) ** 2 + 63) // 64
+            return "sipdg::g3::k3gm<double, %d, %d, %d, %d, %d>" % (order, e, nw, 2 if geo_map else 0, bud)
         return "sipdg::g3::k3g<double, %d, 1, %d>" % (order, 2 if geo_map else 0)
     if variant == "gather_fold_persistent" and order == 0:
         return "sipdg::g3::k3g_persistent<double, %d>" % (0 if stage == 1 else 1)
@@ -227,6 +233,7 @@ def bench_2d(args, stream):
         m = synth.workload(k)
         st = inspect_mesh(m)
         op = SipdgOperator(m)
+        tuned = op.autotune(20)
         x = torch.tensor(synth.random_coefficients(m, 4000 + k), device="cuda")
         y = torch.empty_like(x)
         x32, y32 = x.float(), torch.empty_like(x, dtype=torch.float32)
@@ -245,6 +252,7 @@ def bench_2d(args, stream):
             "apply_us": ms * 1e3, "gdofs": op.n_dofs / (ms * 1e-3) / 1e9,
             "apply_fp32_us": ms32 * 1e3, "gdofs_fp32": op.n_dofs / (ms32 * 1e-3) / 1e9,
             "launches_per_apply": len(op.apply_timed(x, y, reps=5, stream=stream)),
+            "variant": op.variant, "autotune_ms": tuned,
             "cg_f64": solve_record(info, op.n_dofs, algorithmic_bytes(st, 2, 8), 8),
         }
         op.close()
@@ -414,7 +422,8 @@ def main():
     achieved = b64 / (ms * 1e-3) / 1e9
     apply_launches = [L for L in launches if L["stage"] == 2]
     dom = max(apply_launches, key=lambda L: L["ms"])
-    dom_name = kernel_name(op.variant, dom["order"])
+    tuning = op.tuning()
+    dom_name = kernel_name(op.variant, dom["order"], tuning=tuning)
     traffic = traffic_app = None
     if os.path.exists(args.traffic):
         try:
@@ -459,7 +468,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_app, "algorithmic_bytes": b64,
             "kernels": "all launches of one application (kernel structure: %s)" % op.variant,
         },
-        "launches": [{"kernel": kernel_name(op.variant, L["order"], L["stage"]), "ms": L["ms"],
+        "launches": [{"kernel": kernel_name(op.variant, L["order"], L["stage"], tuning=tuning), "ms": L["ms"],
                       "elements": L["elements"],
                       "gbs": (L["alg_bytes"] / (L["ms"] * 1e-3) / 1e9) if L["alg_bytes"] else None}
                      for L in launches],
@@ -470,6 +479,7 @@ def main():
         },
         "stages_ms": {"trace": ms_s1, "flux_volume": ms_s2},
         "variant": op.variant,
+        "tile_shapes": {str(p): [tuning["tile"][p], tuning["budget"][p]] for p in range(1, 9)},
         "autotune_ms": tuned,
         "flops": {"algorithmic_per_apply": flops,
                   "tflops": flops / (ms * 1e-3) / 1e12,
@@ -508,7 +518,8 @@ def main():
         lm = op.apply_timed(x, y, reps=max(10, min(args.steps, 100)), stream=stream)
         gm = {"value": ndof / (ms_m * 1e-3) / 1e9, "unit": "GDOF/s", "ms": ms_m,
               "fp32_value": ndof / (ms_m32 * 1e-3) / 1e9, "fp32_ms": ms_m32,
-              "launches": [{"kernel": kernel_name("gather_fold", L["order"], L["stage"], geo_map=True),
+              "launches": [{"kernel": kernel_name("gather_fold", L["order"], L["stage"], geo_map=True,
+                                                  tuning=tuning),
                             "ms": L["ms"]} for L in lm]}
         if not args.no_cg:
             for mode in ("f64", "f32_ir"):

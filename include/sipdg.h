@@ -227,7 +227,13 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
  *              volume's pointwise terms so that one IProduct lifts faces and
  *              volume (Sec. 3.3).  3-D; an order group <= 6 touching a
  *              neighbour above 6 uses the GATHER kernels (same trace buffer).
- *              Default in 3-D (GATHER in 2-D).
+ *              In 2-D: one wavefront per quadrilateral of order <= 6 whose
+ *              faces carry at most 8 trace points, all of them in one trace
+ *              launch and one apply launch; each face side's (u, g) at the
+ *              trace points from the element's coefficients (TracePhysEval),
+ *              the flux lifted by the transposed interpolation and folded
+ *              into the pointwise terms; the other elements on the GATHER
+ *              kernels.  Default in 3-D, and in 2-D when an element fits.
  *   GATHER_FOLD_PERSISTENT: as GATHER_FOLD, but each stage is one
  *              persistent launch for the elements of every order <= 6 of all
  *              problems (listed by decreasing order; a fixed number of blocks
@@ -235,7 +241,9 @@ int sipdg_apply_timed(sipdg_handle h, const void *x, void *y, int precision, int
  *              3-D.
  *   GATHER_FOLD_FUSED: as GATHER_FOLD, but the neighbour's traces are
  *              evaluated from its coefficients (TracePhysEval): one launch
- *              per order group, no trace buffer.  3-D, orders <= 6. */
+ *              per order group, no trace buffer.  3-D, orders <= 6; 2-D
+ *              when every element takes the 2-D wavefront kernel (one launch
+ *              for the whole mesh). */
 #define SIPDG_VARIANT_GATHER            0
 #define SIPDG_VARIANT_TWO_STAGE         1
 #define SIPDG_VARIANT_FUSED             2
@@ -377,7 +385,11 @@ int sipdg_set_tile(sipdg_handle h, int order, int tile, int budget);
 int sipdg_apply_transpose(sipdg_handle h, const void *g, void *xbar, int precision,
                           void *stream);
 
-/* d = diag(A) in FP64 (device [n_dofs]), async. */
+/* d = diag(A) in FP64 (device [n_dofs]), async: a(phi_i, phi_i) of eq. IP
+ * with the neighbours' coefficients zero, sum-factorised per element (every
+ * volume and face term of the diagonal is a tensor contraction of squared
+ * 1-D mode tables with the geometric factors).  The Jacobi preconditioner of
+ * sipdg_cg_solve. */
 int sipdg_diagonal(sipdg_handle h, double *d, void *stream);
 
 /* Gradients of the scalar a^T A b with respect to the parameters (the
@@ -500,7 +512,12 @@ int sipdg_gmres_solve(sipdg_handle h, const double *b, double *x, const sipdg_gm
  * FP32 inner solves inside FP64 iterative refinement (mode, a project
  * addition).  b, x: device FP64 [n_dofs], owned by the caller (x is the
  * initial guess when opts->x0_given).  CG iterations are captured in HIP
- * graphs of opts->graph_k iterations.  Synchronous: returns when done.
+ * graphs of opts->graph_k iterations.  When the 3-D gather-fold structure
+ * evaluates every element's traces in one launch, each iteration's updates
+ * of x and of the search direction run inside the next application's trace
+ * stage (one pass over r, p and x instead of two vector kernels; the same
+ * values bit for bit; the environment variable SIPDG_NO_FOLD=1 keeps the
+ * separate kernels).  Synchronous: returns when done.
  * Errors: ENOCONV (maxit reached, info filled), EBREAKDOWN (p^T A p <= 0),
  * EINVAL (null pointer, options, point-to-point flux set), EHIP. */
 int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_opts *opts,

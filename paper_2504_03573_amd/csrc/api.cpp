@@ -147,6 +147,23 @@ static bool gfold_group(const Group &g, bool fused) {
     return !fused && g.P >= 7 && g.P <= 8 && g.nfmax <= 10;
 }
 
+// Kernel structures of a 2-D handle: the general kernels, the wavefront
+// kernels (an element of order <= 6 with traces <= 8 points needed), and the
+// fused wavefront kernel (every element in the wavefront list).
+static bool variant_allowed_2d(const sipdg_ctx *c, int v) {
+    if (v == SIPDG_VARIANT_GATHER) return true;
+    if (v == SIPDG_VARIANT_GATHER_FOLD) return c->w2count > 0;
+    if (v == SIPDG_VARIANT_GATHER_FOLD_FUSED) return c->w2count > 0 && c->w2count == c->ne;
+    return false;
+}
+
+// Default kernel structure: gather-fold in 3-D and, in 2-D, the wavefront
+// kernels when an element can take them; the general kernels otherwise.
+static int default_variant(const sipdg_ctx *c) {
+    if (c->dim == 3) return c->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
+    return c->w2count > 0 ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
+}
+
 // per-element constants of affine elements (G~, |J|), in the apply's precision
 template <class R>
 static const R *egeo_of(const sipdg_ctx *c) {
@@ -177,12 +194,58 @@ static hipError_t launch_apply_group(const sipdg_ctx *c, int P, int mode, int nf
     return launch_gfold3d<R>(P, mode, nfmax, A, D, st);
 }
 
+bool fold_ok(const sipdg_ctx *c) {
+    return c->dim == 3 && c->variant == SIPDG_VARIANT_GATHER_FOLD && c->flux == SIPDG_FLUX_SHARED &&
+           c->pcount == c->ne && c->ne > 0 && c->d_eprob != nullptr;
+}
+
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages,
-               LaunchRec *rec) {
+               LaunchRec *rec, const CgFold<R> *fold) {
+    if (fold && (!fold_ok(c) || fold->p != x))
+        return fail(SIPDG_EINVAL, "internal: folded CG step on an apply that cannot take it");
     const bool gauss = c->points == SIPDG_POINTS_GAUSS;
     if (gauss && (c->variant != SIPDG_VARIANT_GATHER_FOLD || c->flux != SIPDG_FLUX_SHARED))
         return fail(SIPDG_EINVAL, "Gauss points run on the gather_fold structure with the shared-trace flux");
+    if (c->dim == 2 && (c->variant == SIPDG_VARIANT_GATHER_FOLD || c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED)) {
+        // 2-D wavefront kernels: one launch per stage for every element of
+        // order <= 6 with traces <= 8 points; the general kernels for the
+        // groups around orders 7 and 8 (same trace-buffer layout).  The fused
+        // structure (one launch) is allowed only when the wavefront list
+        // holds every element.
+        if (c->groups.empty()) return SIPDG_OK;
+        const bool fused = c->variant == SIPDG_VARIANT_GATHER_FOLD_FUSED;
+        Data2<R> D2;
+        {
+            f3::Args3 A3;
+            f3::Data3<R> D3;
+            fast_args<R>(c, c->groups[0], x, y, tbuf, skip, false, A3, D3);
+            D2 = Data2<R>{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, x, y, tbuf};
+        }
+        const Args2 A2{c->d_w2desc, c->d_w2fdesc, c->w2count, c->d_faces, c->d_order, c->d_xoff, skip};
+        for (int stage = 1; stage <= 2; ++stage) {
+            if (!(stages & stage) || (fused && stage == 1)) continue;
+            if (c->w2count > 0) {
+                rec_mark(rec, stage, -1, false, st);
+                hipError_t e = launch_wave2d<R>(stage == 1 ? 0 : (fused ? 2 : 1), A2, D2, st);
+                rec_mark(rec, stage, -1, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string("2-D wavefront kernel: ") + hipGetErrorString(e));
+            }
+            for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+                const Group &g = c->groups[gi];
+                if (g.P <= 6 && g.nfmax <= 8) continue;
+                OpArgs<R> A = make_args<R>(c, g, x, y, tbuf, skip);
+                rec_mark(rec, stage, (int)gi, false, st);
+                hipError_t e = launch_op<R>(c->dim, g.P, stage == 1 ? OP_TRACE : OP_APPLY, A, g.nfmax, st);
+                rec_mark(rec, stage, (int)gi, true, st);
+                if (e != hipSuccess)
+                    return fail(SIPDG_EHIP, std::string(stage == 1 ? "trace kernel: " : "apply kernel: ") +
+                                                hipGetErrorString(e));
+            }
+        }
+        return SIPDG_OK;
+    }
     if (c->flux == SIPDG_FLUX_P2P && c->variant != SIPDG_VARIANT_GATHER) {
         // point-to-point flux through the gather-fold apply: per order group a
         // trace launch (own pair, and the trace interpolated to each
@@ -322,6 +385,16 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
                 g3::Args A{A3.elems, c->pcount, A3.xoff, A3.voff, A3.eface, A3.faces, A3.order, A3.foff, A3.toff,
                            A3.skip, c->d_pdesc, c->d_pfdesc, c->basis};
                 g3::Data<R> D{D3.vgeo, D3.fgeo, D3.lam, D3.tau, D3.tab, D3.x, D3.y, D3.tbuf, egeo_of<R>(c), emap_of<R>(c)};
+                if (fold) {
+                    D.fold_p = fold->p;
+                    D.fold_x = fold->x;
+                    D.fold_r = fold->r;
+                    D.fold_dinv = fold->dinv;
+                    D.fold_alpha = fold->alpha;
+                    D.fold_beta = fold->beta;
+                    D.fold_conv = fold->conv;
+                    D.eprob = c->d_eprob;
+                }
                 rec_mark(rec, stage, -1, false, main_st);
                 hipError_t e = launch_gfold3d_trace_all<R>(A, D, main_st);
                 rec_mark(rec, stage, -1, true, main_st);
@@ -462,9 +535,9 @@ int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStre
     return SIPDG_OK;
 }
 template int apply_impl<double>(sipdg_ctx *, const double *, double *, double *, const int *, hipStream_t, int,
-                                LaunchRec *);
+                                LaunchRec *, const CgFold<double> *);
 template int apply_impl<float>(sipdg_ctx *, const float *, float *, float *, const int *, hipStream_t, int,
-                               LaunchRec *);
+                               LaunchRec *, const CgFold<float> *);
 
 int refresh_diag(sipdg_ctx *c, hipStream_t st) {
     hipError_t e = launch_diag(c->dim, c->ne, c->d_order, c->d_xoff, c->d_voff, c->d_eface, c->d_foff,
@@ -496,7 +569,7 @@ static void free_ctx(sipdg_ctx *c) {
                     c->d_tau64, c->d_vgeo32, c->d_fgeo32, c->d_lam32, c->d_tau32, c->d_tau0,
                     c->d_tbuf, c->d_tbuf2, c->d_face_tmp, c->d_elem_tmp, c->d_diag64,
                     c->d_dinv64, c->d_dinv32, c->d_egeo64, c->d_egeo32, c->d_emap64, c->d_emap32,
-                    c->d_tbuf_p2p, c->d_p2p_side, c->d_fgeo_p2p64, c->d_fgeo_p2p32,
+                    c->d_tbuf_p2p, c->d_p2p_side, c->d_fgeo_p2p64, c->d_fgeo_p2p32, c->d_w2desc, c->d_w2fdesc, c->d_eprob,
                     c->d_pfdesc_p2p, c->d_tabgl64, c->d_tabgl32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -813,6 +886,30 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
     {
         int pmax = 0;
         for (int o : T.order) pmax = std::max(pmax, o);
+        if (T.dim == 2) {
+            // the 2-D wavefront list: elements of order <= 6 whose faces have
+            // at most 8 trace points, by decreasing order
+            std::vector<ElemDesc> wd;
+            std::vector<FaceDesc> wf;
+            for (int P = 6; P >= 1; --P) {
+                for (int64_t e = 0; e < T.ne; ++e) {
+                    if (T.order[e] != P) continue;
+                    int nfm = 0;
+                    for (int f = 0; f < 4; ++f) nfm = std::max(nfm, face_nf(T.eface[(size_t)e * 4 + f].info));
+                    if (nfm > 8) continue;
+                    wd.push_back(ElemDesc{T.xoff[e], T.voff[e], (int)e, P});
+                    for (int f = 0; f < 4; ++f) {
+                        const FaceRef fr = T.eface[(size_t)e * 4 + f];
+                        wf.push_back(FaceDesc{T.foff[fr.F], T.toff[fr.F], fr.F, fr.info});
+                    }
+                }
+            }
+            c->w2count = (int)wd.size();
+            if (!wd.empty()) {
+                TRY(upload(&c->d_w2desc, wd));
+                TRY(upload(&c->d_w2fdesc, wf));
+            }
+        }
         if (T.dim == 3) {
             std::vector<ElemDesc> pd;
             std::vector<FaceDesc> pf;
@@ -858,7 +955,7 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
         c->gfold_ok = T.dim == 3;
         c->fast_ok0 = c->fast_ok;
         c->gfold_ok0 = c->gfold_ok;
-        c->variant = c->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
+        c->variant = default_variant(c);
         const char *env = std::getenv("SIPDG_VARIANT");
         if (env && c->gfold_ok) {
             std::string v(env);
@@ -880,6 +977,13 @@ static int create_impl(int nprob, const sipdg_mesh_desc *descs, sipdg_handle *ou
     TRY(dalloc(&c->d_face_tmp, std::max<int64_t>(1, c->nfaces)));
     TRY(dalloc(&c->d_elem_tmp, std::max<int64_t>(1, c->ne)));
     TRY(alloc_cg(c));
+    {
+        // element -> problem (the folded CG step reads its problem's scalars)
+        std::vector<int> ep(std::max<int64_t>(1, c->ne), 0);
+        for (int p = 0; p < c->nprob; ++p)
+            for (int64_t e = c->prob_elem_off[p]; e < c->prob_elem_off[p + 1]; ++e) ep[e] = p;
+        TRY(upload(&c->d_eprob, ep));
+    }
     // the allocation-free apply's scratch address on this device
     TRY(noalloc_setup(c->device));
     c->signature = mesh_signature(T);
@@ -1339,7 +1443,7 @@ int sipdg_set_basis(sipdg_handle h, int basis) {
     // endpoint values in closed form; gather and gather-fold take either basis
     h->fast_ok = basis == SIPDG_BASIS_LEGENDRE && h->fast_ok0;
     h->gfold_ok = h->gfold_ok0;
-    h->variant = h->gfold_ok ? SIPDG_VARIANT_GATHER_FOLD : SIPDG_VARIANT_GATHER;
+    h->variant = default_variant(h);
     if (h->ne > 0) {
         int rc = refresh_diag(h, 0);
         if (rc) return rc;
@@ -1497,6 +1601,15 @@ int sipdg_set_variant(sipdg_handle h, int variant) {
     if (!h) return fail(SIPDG_EINVAL, "null handle");
     if (h->points == SIPDG_POINTS_GAUSS && variant != SIPDG_VARIANT_GATHER_FOLD)
         return fail(SIPDG_EINVAL, "Gauss volume points run on the gather_fold structure only");
+    if (h->dim == 2) {
+        if (!variant_allowed_2d(h, variant))
+            return fail(SIPDG_EINVAL, variant == SIPDG_VARIANT_GATHER_FOLD_FUSED
+                                          ? "2-D gather_fold_fused needs every element of order <= 6 with traces <= 8 points"
+                                          : "2-D meshes take gather, gather_fold (an element of order <= 6) or "
+                                            "gather_fold_fused");
+        h->variant = variant;
+        return SIPDG_OK;
+    }
     if (variant == SIPDG_VARIANT_GATHER) {
         h->variant = variant;
         return SIPDG_OK;
@@ -1579,7 +1692,8 @@ int sipdg_autotune(sipdg_handle h, const char *cache_path, int reps, double *ms_
     for (int v = 0; v < SIPDG_NUM_VARIANTS && rc == SIPDG_OK; ++v) {
         rec.ms[v] = 0.0;
         const bool gf = v == SIPDG_VARIANT_GATHER_FOLD || v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT;
-        if (gf ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)) continue;
+        if (h->dim == 2 ? !variant_allowed_2d(h, v) : (gf ? !h->gfold_ok : (v != SIPDG_VARIANT_GATHER && !h->fast_ok)))
+            continue;
         if (v == SIPDG_VARIANT_GATHER_FOLD_PERSISTENT && h->basis != SIPDG_BASIS_LEGENDRE) continue;
         h->variant = v;
         double vbest = 1e300;
@@ -1597,7 +1711,7 @@ int sipdg_autotune(sipdg_handle h, const char *cache_path, int reps, double *ms_
                 }
             }
             h->blocks_per_cu = vshape;
-        } else if (v == SIPDG_VARIANT_GATHER_FOLD) {
+        } else if (v == SIPDG_VARIANT_GATHER_FOLD && h->dim == 3) {
             // tile shape of each order group's apply launch, one order at a
             // time (the others fixed at their best so far)
             rc = time_apply(vbest);

@@ -24,9 +24,22 @@ int fail(int code, const std::string &msg);
 template <class R>
 OpArgs<R> make_args(const sipdg_ctx *c, const Group &g, const R *x, R *y, R *tbuf, const int *skip);
 
+// One CG step folded into the apply's trace stage (see g3::Data): x of the
+// apply is the search direction p.
+template <class R>
+struct CgFold {
+    R *p, *x;
+    const R *r, *dinv;   // dinv null: no preconditioner
+    const double *alpha, *beta;
+    const int *conv;
+};
+
 template <class R>
 int apply_impl(sipdg_ctx *c, const R *x, R *y, R *tbuf, const int *skip, hipStream_t st, int stages = 3,
-               LaunchRec *rec = nullptr);
+               LaunchRec *rec = nullptr, const CgFold<R> *fold = nullptr);
+// Can the handle's current apply take a folded CG step?  (3-D gather-fold
+// structure, shared-trace flux, every element in the one trace launch.)
+bool fold_ok(const sipdg_ctx *c);
 
 int refresh_diag(sipdg_ctx *c, hipStream_t st);
 void free_cg(sipdg_ctx *c);

@@ -173,85 +173,189 @@ __global__ void k_points(const double *corners, const int *order, const FaceRef 
     }
 }
 
-// Jacobi diagonal a(phi_i, phi_i): one block per element, one thread per mode;
-// every basis function and its reference gradient is formed from the 1-D
-// Legendre tables at the volume points and at the trace points.
+// Jacobi diagonal a(phi_i, phi_i), sum-factorised, one block per element.
+// Every term of the bilinear form at i = j factorises over the reference
+// directions, so each is a tensor contraction with squared 1-D tables:
+//  * volume: sum_q G_ab(q) g_a g_b, with g_a = D(q_a, i_a) prod_{c != a} B(q_c, i_c),
+//    is the contraction of the per-point factor G_ab with, per direction d,
+//    D^2 (d = a = b), B D (d one of a != b) or B^2 (otherwise); the lambda
+//    term contracts w|J| with B^2 in every direction;
+//  * face (k, s) at trace points t = (t1, t2) in the element's face
+//    coordinates (directions a < b, both != k): phi = v_k(i_k) Bf(t1, i_a) Bf(t2, i_b)
+//    with v_k, dv_k the mode values and derivatives at the end xi_k = s, and
+//    phi (n.grad phi) w J_s = v_k dv_k C_k Bf^2 Bf^2 + v_k^2 (C_a (Bf Df) Bf^2 + C_b Bf^2 (Bf Df)),
+//    so the face adds v_k^2 S_vv(i_a, i_b) + v_k dv_k S_vd(i_a, i_b) with two
+//    2-D contractions over the trace (value-test and gradient-test terms of
+//    eq. IP with the neighbour's coefficients zero; boundary faces by the
+//    mirrored value, twice the consistency and penalty terms).
+// The operation count is O(n^{d+1}) per term instead of O(n^d N_P^d).
 template <int DIM>
-__global__ void k_diag(const int *order, const int64_t *xoff, const int64_t *voff,
-                       const FaceRef *eface, const int64_t *foff, const double *vgeo,
-                       const double *fgeo, const double *lam, const double *tau,
-                       const double *tab, double *diag) {
+__global__ __launch_bounds__(256) void k_diag(const int *order, const int64_t *xoff, const int64_t *voff,
+                                              const FaceRef *eface, const int64_t *foff, const double *vgeo,
+                                              const double *fgeo, const double *lam, const double *tau,
+                                              const double *tab, double *diag) {
+    constexpr int S = PMAX + 1, NM3 = DIM == 3 ? NMAX * NMAX * NMAX : NMAX * NMAX;
+    constexpr int NG = DIM * (DIM + 1) / 2 + 1;
+    __shared__ double T[3][NMAX * S];   // B^2, D^2, B D at the volume points [q][i]
+    __shared__ double G[NM3];           // one geometric factor at the volume points
+    __shared__ double W1[NM3], W2[NM3]; // partial contractions
+    __shared__ double acc[NM3];         // the diagonal of this element's modes
+    __shared__ double FT[2][NMAX * S];  // Bf^2, Bf Df at the trace points [t][i]
+    __shared__ double FW[4][NMAX * NMAX];   // a, C_k, C_a, C_b at (t1, t2)
+    __shared__ double Y[3][NMAX * S];   // first face contraction [t2][i_a]
+    __shared__ double SV[2][S * S];     // S_vv, S_vd [i_b][i_a]
     const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int P = order[e], n = P + 2, np = P + 1;
     const int nm = DIM == 3 ? np * np * np : np * np;
     const int npts = DIM == 3 ? n * n * n : n * n;
-    constexpr int NG = DIM * (DIM + 1) / 2 + 1;
-    constexpr int S = PMAX + 1;
     const double *Bn = tab + tab_off_BF(n), *Dn = tab + tab_off_DBF(n);
     const double *gb = vgeo + voff[e];
-    for (int i = threadIdx.x; i < nm; i += blockDim.x) {
-        const int ii[3] = {i % np, (i / np) % np, DIM == 3 ? i / (np * np) : 0};
-        double val = 0.0;
-        for (int q = 0; q < npts; ++q) {
-            const int qq[3] = {q % n, (q / n) % n, DIM == 3 ? q / (n * n) : 0};
-            double phi = 1.0, g[3];
-            for (int a = 0; a < DIM; ++a) phi *= Bn[qq[a] * S + ii[a]];
-            for (int a = 0; a < DIM; ++a) {
-                double t = Dn[qq[a] * S + ii[a]];
-                for (int b = 0; b < DIM; ++b)
-                    if (b != a) t *= Bn[qq[b] * S + ii[b]];
-                g[a] = t;
-            }
-            int c = 0;
-            double s = 0.0;
-            for (int a = 0; a < DIM; ++a)
-                for (int b = a; b < DIM; ++b) {
-                    const double G = gb[(c++) * npts + q];
-                    s += (a == b ? 1.0 : 2.0) * G * g[a] * g[b];
-                }
-            val += s + lam[e] * gb[(NG - 1) * npts + q] * phi * phi;
-        }
-        for (int f = 0; f < 2 * DIM; ++f) {
-            const FaceRef fr = eface[e * 2 * DIM + f];
-            const int nf = face_nf(fr.info), slot = face_slot(fr.info), o = face_orient(fr.info);
-            const int k = f / 2, end = (f & 1) ? n - 1 : 0;
-            const int npf = DIM == 3 ? nf * nf : nf;
-            const double *Bf = tab + tab_off_BF(nf), *Df = tab + tab_off_DBF(nf);
-            const double *fg = fgeo + foff[fr.F];
-            const int gs = slot == 2 ? 0 : slot;
-            const double tf = tau[fr.F];
-            int dims[2], j = 0;
-            for (int a = 0; a < DIM; ++a)
-                if (a != k) dims[j++] = a;
-            for (int t = 0; t < npf; ++t) {
-                const int t1 = t % nf, t2 = DIM == 3 ? t / nf : 0;
-                const int qc = DIM == 3 ? canon_index(o, nf, t1, t2) : ((o & 1) ? nf - 1 - t1 : t1);
-                // 1-D factors per reference direction at this trace point
-                double v[3], dv[3];
-                v[k] = Bn[end * S + ii[k]];
-                dv[k] = Dn[end * S + ii[k]];
-                v[dims[0]] = Bf[t1 * S + ii[dims[0]]];
-                dv[dims[0]] = Df[t1 * S + ii[dims[0]]];
-                if (DIM == 3) {
-                    v[dims[1]] = Bf[t2 * S + ii[dims[1]]];
-                    dv[dims[1]] = Df[t2 * S + ii[dims[1]]];
-                }
-                double phi = 1.0;
-                for (int a = 0; a < DIM; ++a) phi *= v[a];
-                double gn = 0.0;
-                for (int m = 0; m < DIM; ++m) {
-                    double gm = dv[m];
-                    for (int b = 0; b < DIM; ++b)
-                        if (b != m) gm *= v[b];
-                    gn += fg[npf * (1 + DIM * gs) + m * npf + qc] * gm;
-                }
-                const double a = fg[qc];
-                if (slot == 2) val += -2.0 * phi * gn + 2.0 * tf * a * phi * phi;
-                else val += -phi * gn + tf * a * phi * phi;
-            }
-        }
-        diag[xoff[e] + i] = val;
+    for (int i = tid; i < n * np; i += nt) {
+        const int q = i / np, j = i - q * np;
+        const double b = Bn[q * S + j], d = Dn[q * S + j];
+        T[0][q * S + j] = b * b;
+        T[1][q * S + j] = d * d;
+        T[2][q * S + j] = b * d;
     }
+    for (int i = tid; i < nm; i += nt) acc[i] = 0.0;
+    __syncthreads();
+    // volume: components 00 01 02 11 12 22 (2-D: 00 01 11), then w|J| (lambda)
+    int c = 0;
+    for (int ta = 0; ta <= DIM; ++ta) {
+        for (int tb = ta; tb < DIM || (ta == DIM && tb == DIM); ++tb) {
+            const bool mass = ta == DIM;
+            const double coef = mass ? lam[e] : (ta == tb ? 1.0 : 2.0);
+            // table per direction: 0 = B^2, 1 = D^2, 2 = B D
+            int td[3];
+            for (int d = 0; d < 3; ++d)
+                td[d] = mass ? 0 : (ta == d && tb == d ? 1 : ((ta == d || tb == d) ? 2 : 0));
+            const double *gc = gb + (int64_t)(mass ? NG - 1 : c) * npts;
+            for (int q = tid; q < npts; q += nt) G[q] = coef * gc[q];
+            __syncthreads();
+            const double *T0 = T[td[0]], *T1 = T[td[1]], *T2 = T[td[2]];
+            if (DIM == 3) {
+                // q0 -> i0: W1[i0 + np (q1 + n q2)]
+                for (int i = tid; i < np * n * n; i += nt) {
+                    const int i0 = i % np, r = i / np;
+                    double s = 0.0;
+                    for (int q = 0; q < n; ++q) s += T0[q * S + i0] * G[q + n * r];
+                    W1[i] = s;
+                }
+                __syncthreads();
+                // q1 -> i1: W2[i0 + np (i1 + np q2)]
+                for (int i = tid; i < np * np * n; i += nt) {
+                    const int i0 = i % np, i1 = (i / np) % np, q2 = i / (np * np);
+                    double s = 0.0;
+                    for (int q = 0; q < n; ++q) s += T1[q * S + i1] * W1[i0 + np * (q + n * q2)];
+                    W2[i] = s;
+                }
+                __syncthreads();
+                // q2 -> i2
+                for (int i = tid; i < nm; i += nt) {
+                    const int i01 = i % (np * np), i2 = i / (np * np);
+                    double s = 0.0;
+                    for (int q = 0; q < n; ++q) s += T2[q * S + i2] * W2[i01 + np * np * q];
+                    acc[i] += s;
+                }
+            } else {
+                for (int i = tid; i < np * n; i += nt) {
+                    const int i0 = i % np, q1 = i / np;
+                    double s = 0.0;
+                    for (int q = 0; q < n; ++q) s += T0[q * S + i0] * G[q + n * q1];
+                    W1[i] = s;
+                }
+                __syncthreads();
+                for (int i = tid; i < nm; i += nt) {
+                    const int i0 = i % np, i1 = i / np;
+                    double s = 0.0;
+                    for (int q = 0; q < n; ++q) s += T1[q * S + i1] * W1[i0 + np * q];
+                    acc[i] += s;
+                }
+            }
+            __syncthreads();
+            if (mass) break;
+            ++c;
+        }
+    }
+    // faces
+    for (int f = 0; f < 2 * DIM; ++f) {
+        const FaceRef fr = eface[e * 2 * DIM + f];
+        const int nf = face_nf(fr.info), slot = face_slot(fr.info), o = face_orient(fr.info);
+        const int k = f / 2, end = (f & 1) ? n - 1 : 0;
+        const int npf = DIM == 3 ? nf * nf : nf;
+        const double *Bf = tab + tab_off_BF(nf), *Df = tab + tab_off_DBF(nf);
+        const double *fg = fgeo + foff[fr.F];
+        const int gs = slot == 2 ? 0 : slot;
+        const double cw = slot == 2 ? 2.0 : 1.0;   // boundary: mirrored value
+        const double tp = cw * tau[fr.F];
+        const int da = k == 0 ? 1 : 0, db = k == 2 ? 1 : 2;
+        for (int i = tid; i < nf * np; i += nt) {
+            const int t = i / np, j = i - t * np;
+            const double b = Bf[t * S + j], d = Df[t * S + j];
+            FT[0][t * S + j] = b * b;
+            FT[1][t * S + j] = b * d;
+        }
+        for (int t = tid; t < npf; t += nt) {
+            const int t1 = t % nf, t2 = DIM == 3 ? t / nf : 0;
+            const int qc = DIM == 3 ? canon_index(o, nf, t1, t2) : ((o & 1) ? nf - 1 - t1 : t1);
+            const double *Cs = fg + npf * (1 + DIM * gs) + qc;
+            FW[0][t] = tp * fg[qc];
+            FW[1][t] = -cw * Cs[k * npf];
+            FW[2][t] = -cw * Cs[da * npf];
+            FW[3][t] = DIM == 3 ? -cw * Cs[db * npf] : 0.0;
+        }
+        __syncthreads();
+        if (DIM == 3) {
+            // along t1: Y0 = B2 a' + BD Ca', Y1 = B2 Cb', Y2 = B2 Ck'  [t2][i_a]
+            for (int i = tid; i < nf * np; i += nt) {
+                const int t2 = i / np, ia = i - t2 * np;
+                double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+                for (int t1 = 0; t1 < nf; ++t1) {
+                    const int t = t1 + nf * t2;
+                    const double b2 = FT[0][t1 * S + ia], bd = FT[1][t1 * S + ia];
+                    y0 += b2 * FW[0][t] + bd * FW[2][t];
+                    y1 += b2 * FW[3][t];
+                    y2 += b2 * FW[1][t];
+                }
+                Y[0][t2 * S + ia] = y0;
+                Y[1][t2 * S + ia] = y1;
+                Y[2][t2 * S + ia] = y2;
+            }
+            __syncthreads();
+            for (int i = tid; i < np * np; i += nt) {
+                const int ib = i / np, ia = i - ib * np;
+                double vv = 0.0, vd = 0.0;
+                for (int t2 = 0; t2 < nf; ++t2) {
+                    const double b2 = FT[0][t2 * S + ib], bd = FT[1][t2 * S + ib];
+                    vv += b2 * Y[0][t2 * S + ia] + bd * Y[1][t2 * S + ia];
+                    vd += b2 * Y[2][t2 * S + ia];
+                }
+                SV[0][ib * S + ia] = vv;
+                SV[1][ib * S + ia] = vd;
+            }
+        } else {
+            for (int ia = tid; ia < np; ia += nt) {
+                double vv = 0.0, vd = 0.0;
+                for (int t1 = 0; t1 < nf; ++t1) {
+                    const double b2 = FT[0][t1 * S + ia], bd = FT[1][t1 * S + ia];
+                    vv += b2 * FW[0][t1] + bd * FW[2][t1];
+                    vd += b2 * FW[1][t1];
+                }
+                SV[0][ia] = vv;
+                SV[1][ia] = vd;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < nm; i += nt) {
+            const int ii[3] = {i % np, (i / np) % np, DIM == 3 ? i / (np * np) : 0};
+            const double v = Bn[end * S + ii[k]], dv = Dn[end * S + ii[k]];
+            const int s2 = DIM == 3 ? ii[db] * S + ii[da] : ii[da];
+            acc[i] += v * v * SV[0][s2] + v * dv * SV[1][s2];
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < nm; i += nt) diag[xoff[e] + i] = acc[i];
 }
 
 // Interior-face part of d(a^T A b)/d sigma: per face

@@ -169,6 +169,12 @@ struct sipdg_ctx {
     sipdg::ElemDesc *d_pdesc = nullptr;
     sipdg::FaceDesc *d_pfdesc = nullptr;
     int pcount = 0;
+    // 2-D wavefront list: every element of order <= 6 with traces <= 8
+    // points, by decreasing order (ElemDesc::pad = order), four faces each
+    sipdg::ElemDesc *d_w2desc = nullptr;
+    sipdg::FaceDesc *d_w2fdesc = nullptr;
+    int w2count = 0;
+    int *d_eprob = nullptr;   // [n_elems] problem of each element
     int num_cu = 256;
     int blocks_per_cu = 8;            // persistent grid = num_cu * blocks_per_cu
     uint64_t signature = 0;           // mesh signature (autotuner cache key)

@@ -127,6 +127,20 @@ struct Data {
     R *__restrict__ tbuf;
     const R *__restrict__ egeo;   // [ne][8]: G~ (00 01 02 11 12 22), |J| of affine elements
     const R *__restrict__ emap;   // [ne][24]: trilinear map coefficients c1..c7 (x, y, z), pad
+    // One conjugate-gradient step folded into the trace stage (k3t_all with
+    // FOLD only): the coefficients are the search direction p, and before
+    // they are used the element's entries get  x += alpha p  (the previous
+    // step's update, deferred) and  p = D^-1 r + beta p  (p kept for a
+    // stopped problem), with alpha, beta, the stop flag of the element's
+    // problem (eprob: element -> problem).  fold_dinv null: no preconditioner.
+    R *fold_p = nullptr;
+    R *fold_x = nullptr;
+    const R *fold_r = nullptr;
+    const R *fold_dinv = nullptr;
+    const double *fold_alpha = nullptr;
+    const double *fold_beta = nullptr;
+    const int *fold_conv = nullptr;
+    const int *eprob = nullptr;
 };
 
 // Rows of adj(J) and det J of the trilinear map with coefficients c1..c7
@@ -1419,7 +1433,7 @@ struct TSz {
     static constexpr int TOTAL = XS + NU + NW + BT;
 };
 
-template <class R, int P, int BASIS = 0, bool P2P = false>
+template <class R, int P, int BASIS = 0, bool P2P = false, bool FOLD = false>
 __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int blk, unsigned char *smem_raw) {
     using T = TSz<P>;
     constexpr int NP = T::NP, N = T::N, WG = T::W, SG = Geo<P>::S, NM = NP * NP * NP;
@@ -1452,7 +1466,38 @@ __device__ __forceinline__ void k3t_elem(const Args &A, const Data<R> &D, int bl
     // issued before the first store
     constexpr int XIT = (NM + WG - 1) / WG, BIT = (T::BT / 2 + WG - 1) / WG;
     R xv[XIT], bv[2 * BIT];
-    {
+    if constexpr (FOLD) {
+        // the CG step on this element's entries (arithmetic as the separate
+        // vector kernels: in FP64, rounded to R once per stored value)
+        const int pr = D.eprob[ed.e];
+        const double al = D.fold_alpha[pr], be = D.fold_beta[pr];
+        const bool stop = D.fold_conv[pr] != 0;
+        R *__restrict__ pe = D.fold_p + ed.xoff;
+        R *__restrict__ xe = D.fold_x + ed.xoff;
+        const R *__restrict__ re = D.fold_r + ed.xoff;
+        const R *__restrict__ de = D.fold_dinv ? D.fold_dinv + ed.xoff : nullptr;
+        R po[XIT], xo[XIT], ro[XIT], dv[XIT];
+#pragma unroll
+        for (int it = 0; it < XIT; ++it) {
+            const int i = l + it * WG;
+            const int j = (it + 1) * WG <= NM || i < NM ? i : 0;
+            po[it] = pe[j];
+            xo[it] = xe[j];
+            ro[it] = re[j];
+            dv[it] = de ? de[j] : R(1);
+        }
+#pragma unroll
+        for (int it = 0; it < XIT; ++it) {
+            const int i = l + it * WG;
+            const R z = de ? (R)((double)dv[it] * (double)ro[it]) : ro[it];
+            const R pn = stop ? po[it] : (R)((double)z + be * (double)po[it]);
+            xv[it] = (it + 1) * WG <= NM || i < NM ? pn : R(0);
+            if ((it + 1) * WG <= NM || i < NM) {
+                xe[i] = (R)((double)xo[it] + al * (double)po[it]);
+                pe[i] = pn;
+            }
+        }
+    } else {
         const R *__restrict__ xe = D.x + ed.xoff;
 #pragma unroll
         for (int it = 0; it < XIT; ++it) {
@@ -1666,18 +1711,18 @@ __global__ __launch_bounds__(Geo<P>::W) void k3t(Args A, Data<R> D) {
 
 // Trace stage of every element of order <= 6 (traces <= 8 x 8) in one launch:
 // block b takes element b of A.desc / A.fdesc, its order in ElemDesc::pad.
-template <class R, int BASIS = 0, bool P2P = false>
+template <class R, int BASIS = 0, bool P2P = false, bool FOLD = false>
 __global__ __launch_bounds__(W) void k3t_all(Args A, Data<R> D) {
     if (A.skip && *A.skip) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int i = blockIdx.x;
     switch (A.desc[i].pad & ELEM_ORDER_MASK) {
-    case 1: k3t_elem<R, 1, BASIS, P2P>(A, D, i, smem_raw); break;
-    case 2: k3t_elem<R, 2, BASIS, P2P>(A, D, i, smem_raw); break;
-    case 3: k3t_elem<R, 3, BASIS, P2P>(A, D, i, smem_raw); break;
-    case 4: k3t_elem<R, 4, BASIS, P2P>(A, D, i, smem_raw); break;
-    case 5: k3t_elem<R, 5, BASIS, P2P>(A, D, i, smem_raw); break;
-    default: k3t_elem<R, 6, BASIS, P2P>(A, D, i, smem_raw); break;
+    case 1: k3t_elem<R, 1, BASIS, P2P, FOLD>(A, D, i, smem_raw); break;
+    case 2: k3t_elem<R, 2, BASIS, P2P, FOLD>(A, D, i, smem_raw); break;
+    case 3: k3t_elem<R, 3, BASIS, P2P, FOLD>(A, D, i, smem_raw); break;
+    case 4: k3t_elem<R, 4, BASIS, P2P, FOLD>(A, D, i, smem_raw); break;
+    case 5: k3t_elem<R, 5, BASIS, P2P, FOLD>(A, D, i, smem_raw); break;
+    default: k3t_elem<R, 6, BASIS, P2P, FOLD>(A, D, i, smem_raw); break;
     }
 }
 __host__ __device__ constexpr int lds_trace_all() {

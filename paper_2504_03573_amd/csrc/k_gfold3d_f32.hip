@@ -72,6 +72,8 @@ hipError_t launch_gfold3d_trace_all<float>(const g3::Args &A, const g3::Data<flo
     const size_t lds = sizeof(float) * g3::lds_trace_all();
     if (A.side && A.basis) hipLaunchKernelGGL((g3::k3t_all<float, 1, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else if (A.side) hipLaunchKernelGGL((g3::k3t_all<float, 0, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    else if (D.fold_p && A.basis) hipLaunchKernelGGL((g3::k3t_all<float, 1, false, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    else if (D.fold_p) hipLaunchKernelGGL((g3::k3t_all<float, 0, false, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else if (A.basis) hipLaunchKernelGGL((g3::k3t_all<float, 1>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else hipLaunchKernelGGL((g3::k3t_all<float>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     return hipGetLastError();

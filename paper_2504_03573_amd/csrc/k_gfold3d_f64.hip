@@ -72,6 +72,8 @@ hipError_t launch_gfold3d_trace_all<double>(const g3::Args &A, const g3::Data<do
     const size_t lds = sizeof(double) * g3::lds_trace_all();
     if (A.side && A.basis) hipLaunchKernelGGL((g3::k3t_all<double, 1, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else if (A.side) hipLaunchKernelGGL((g3::k3t_all<double, 0, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    else if (D.fold_p && A.basis) hipLaunchKernelGGL((g3::k3t_all<double, 1, false, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
+    else if (D.fold_p) hipLaunchKernelGGL((g3::k3t_all<double, 0, false, true>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else if (A.basis) hipLaunchKernelGGL((g3::k3t_all<double, 1>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     else hipLaunchKernelGGL((g3::k3t_all<double>), dim3(A.count), dim3(g3::W), lds, st, A, D);
     return hipGetLastError();

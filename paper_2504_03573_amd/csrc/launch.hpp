@@ -45,6 +45,33 @@ hipError_t launch_pgrad_elem(int dim, int P, const OpArgs<double> &A, const doub
 struct FaceTopo {
     int eL, fL, eR, fR, orient, nf;
 };
+
+// 2-D wavefront kernels (k2d.hip): every quadrilateral of order <= 6 whose
+// faces carry at most 8 trace points, one wavefront each, one launch.
+struct Args2 {
+    const ElemDesc *desc;    // [count], by decreasing order; pad: order
+    const FaceDesc *fdesc;   // [count][4]
+    int count;
+    const FaceTopo *faces;   // [n_faces] (neighbour lookup of the fused mode)
+    const int *order;        // [n_elems]
+    const int64_t *xoff;     // [n_elems]
+    const int *skip;         // stop flag of a captured solver loop, or null
+};
+template <class R>
+struct Data2 {
+    const R *__restrict__ vgeo;
+    const R *__restrict__ fgeo;
+    const R *__restrict__ lam;
+    const R *__restrict__ tau;
+    const R *__restrict__ tab;
+    const R *__restrict__ x;
+    R *__restrict__ y;
+    R *__restrict__ tbuf;
+};
+// mode 0: trace values into the buffer; 1: apply (neighbours from the
+// buffer); 2: fused apply (neighbours' traces from their coefficients)
+template <class R>
+hipError_t launch_wave2d(int mode, const Args2 &A, const Data2<R> &D, hipStream_t st);
 hipError_t launch_geo_volume(int dim, int64_t ne, const double *corners, const int *order,
                              const int64_t *voff, const double *tab, double *vgeo, int *flag,
                              hipStream_t st);

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -153,9 +154,22 @@ static int ensure_cg32(sipdg_ctx *c) {
     return SIPDG_OK;
 }
 
+// The folded CG step (x and p updated inside the next application's trace
+// stage, see apply_impl) when the handle's apply can take it; the
+// environment variable SIPDG_NO_FOLD=1 keeps the separate vector kernels.
+static bool use_fold(const sipdg_ctx *c) {
+    const char *env = std::getenv("SIPDG_NO_FOLD");
+    return fold_ok(c) && !(env && env[0] == '1');
+}
+
 // One CG iteration in precision R on the work vectors.
+//   separate: q = A p; p.q; alpha; x += alpha p, r -= alpha q, z = M r (with
+//             r.r, r.z); beta; p = z + beta p.
+//   folded:   [x += alpha p, p = M r + beta p, in the trace stage] q = A p;
+//             p.q; alpha; r -= alpha q (with r.r, r.z); beta.  Same values
+//             bit for bit; the last x update is applied by vec_flush.
 template <class R>
-static int cg_body(sipdg_ctx *c, bool precond) {
+static int cg_body(sipdg_ctx *c, bool precond, bool fold) {
     CgWork *w = c->cg;
     hipStream_t st = w->stream;
     R *x, *r, *z, *p, *q;
@@ -167,6 +181,16 @@ static int cg_body(sipdg_ctx *c, bool precond) {
         x = w->x32; r = w->r32; z = w->z32; p = w->pp32; q = w->q32;
         dinv = precond ? c->d_dinv32 : nullptr;
     }
+    if (fold) {
+        const CgFold<R> f{p, x, r, dinv, w->S.alpha, w->S.beta, w->S.conv};
+        int rc = apply_impl<R>(c, p, q, (R *)c->d_tbuf, w->d_done, st, 3, nullptr, &f);
+        if (rc) return rc;
+        HIPCHK(vec_dot<R>(w->V, p, q, w->p1, st));
+        HIPCHK(vec_fin_alpha(w->V, w->S, w->p1, st));
+        HIPCHK(vec_update_fold<R>(w->V, w->S, r, q, dinv, w->p1, w->p2, st));
+        HIPCHK(vec_fin_beta(w->V, w->S, w->p1, w->p2, st));
+        return SIPDG_OK;
+    }
     int rc = apply_impl<R>(c, p, q, (R *)c->d_tbuf, w->d_done, st);
     if (rc) return rc;
     HIPCHK(vec_dot<R>(w->V, p, q, w->p1, st));
@@ -174,6 +198,17 @@ static int cg_body(sipdg_ctx *c, bool precond) {
     HIPCHK(vec_update<R>(w->V, w->S, x, r, p, q, dinv, z, w->p1, w->p2, st));
     HIPCHK(vec_fin_beta(w->V, w->S, w->p1, w->p2, st));
     HIPCHK(vec_pupdate<R>(w->V, w->S, z, p, st));
+    return SIPDG_OK;
+}
+
+// Apply the folded step's pending x update (x += alpha p, then alpha = 0).
+template <class R>
+static int cg_flush(sipdg_ctx *c) {
+    CgWork *w = c->cg;
+    VecCtx Vall = w->V;
+    Vall.done = nullptr;
+    if constexpr (sizeof(R) == 8) HIPCHK(vec_flush<double>(Vall, w->S, w->x64, w->pp64, w->stream));
+    else HIPCHK(vec_flush<float>(Vall, w->S, w->x32, w->pp32, w->stream));
     return SIPDG_OK;
 }
 
@@ -192,7 +227,8 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
     int *gpre = sizeof(R) == 8 ? &w->gpre64 : &w->gpre32;
     int *gop = sizeof(R) == 8 ? &w->gop64 : &w->gop32;
     const int pre = o.precond != 0;
-    const int opk = 32 * c->points + 4 * c->variant + 2 * c->basis + (c->geo_map ? 1 : 0);
+    const bool fold = use_fold(c);
+    const int opk = 64 * (fold ? 1 : 0) + 32 * c->points + 4 * c->variant + 2 * c->basis + (c->geo_map ? 1 : 0);
     if (o.graph_k > 0 && maxit >= k && (*gexec == nullptr || *gk != k || *gpre != pre || *gop != opk)) {
         if (*gexec) {
             (void)hipGraphExecDestroy(*gexec);
@@ -201,7 +237,7 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
         hipGraph_t graph;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         int rc = SIPDG_OK;
-        for (int i = 0; i < k && rc == SIPDG_OK; ++i) rc = cg_body<R>(c, o.precond != 0);
+        for (int i = 0; i < k && rc == SIPDG_OK; ++i) rc = cg_body<R>(c, o.precond != 0, fold);
         hipError_t ec = hipStreamEndCapture(st, &graph);
         if (rc) {
             if (ec == hipSuccess) (void)hipGraphDestroy(graph);
@@ -224,7 +260,7 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
             HIPCHK(hipGraphLaunch(*gexec, st));
         } else {
             for (int i = 0; i < std::min(k, remaining); ++i) {
-                int rc = cg_body<R>(c, o.precond != 0);
+                int rc = cg_body<R>(c, o.precond != 0, fold);
                 if (rc) return rc;
             }
         }
@@ -236,12 +272,20 @@ static int cg_loop(sipdg_ctx *c, const sipdg_cg_opts &o, double tol, int maxit, 
         iters_done = host[0];
         flags = host[1];
         all_done = done;
-        if (allow_ckpt && o.checkpoint && o.checkpoint_every > 0 &&
-            iters_done - last_ckpt >= o.checkpoint_every) {
+        const bool stop = done || (flags & 2) || iters_done >= maxit;
+        const bool ckpt = allow_ckpt && o.checkpoint && o.checkpoint_every > 0 &&
+                          iters_done - last_ckpt >= o.checkpoint_every;
+        if (fold && (stop || ckpt)) {
+            // x is one step behind in the folded iteration: bring it up to date
+            int rc = cg_flush<R>(c);
+            if (rc) return rc;
+            if (ckpt) HIPCHK(hipStreamSynchronize(st));
+        }
+        if (ckpt) {
             o.checkpoint(o.checkpoint_user, w->x64, w->r64, iter_base + iters_done);
             last_ckpt = iters_done;
         }
-        if (done || (flags & 2) || iters_done >= maxit) break;
+        if (stop) break;
     }
     return SIPDG_OK;
 }
@@ -426,7 +470,8 @@ int sipdg_cg_solve(sipdg_handle h, const double *b, double *x, const sipdg_cg_op
                 HIPCHK(vec_start<float>(w->V, w->r32, o.precond ? h->d_dinv32 : nullptr, w->z32, nullptr, w->x32,
                                         w->p1, w->p2, st));
                 HIPCHK(vec_fin_cont(w->V, w->S, w->p1, w->p2, w->d_preconv, w->d_ratio, itol, st));
-                HIPCHK(vec_pupdate<float>(w->V, w->S, w->z32, w->pp32, st));
+                // the folded iteration forms p = M r + beta p itself (alpha is 0)
+                if (!use_fold(h)) HIPCHK(vec_pupdate<float>(w->V, w->S, w->z32, w->pp32, st));
             }
             nr_prev = nr;
             int it = 0, idone = 0;

@@ -38,6 +38,13 @@ hipError_t vec_update(const VecCtx &V, const CgScalars &S, R *x, R *r, const R *
                       const R *dinv, R *z, double *prr, double *prz, hipStream_t st);
 template <class R>
 hipError_t vec_pupdate(const VecCtx &V, const CgScalars &S, const R *z, R *p, hipStream_t st);
+// folded CG step (x and p updated in the next application's trace stage):
+// r -= alpha q with the partials of r.r and r.z, and the deferred x update
+template <class R>
+hipError_t vec_update_fold(const VecCtx &V, const CgScalars &S, R *r, const R *q, const R *dinv, double *prr,
+                           double *prz, hipStream_t st);
+template <class R>
+hipError_t vec_flush(const VecCtx &V, const CgScalars &S, R *x, const R *p, hipStream_t st);
 template <class R>
 hipError_t vec_start(const VecCtx &V, const R *r, const R *dinv, R *z, R *p, R *x, double *prr,
                      double *prz, hipStream_t st);

@@ -61,6 +61,46 @@ __global__ __launch_bounds__(VB) void k_update(VecCtx V, const CgScalars S, R *x
     }
 }
 
+// r -= alpha q; partials of r.r and r.z with z = dinv r (not stored): the
+// update of the folded CG step, whose x and p updates happen in the next
+// application's trace stage (or in k_flush)
+template <class R>
+__global__ __launch_bounds__(VB) void k_update_fold(VecCtx V, const CgScalars S, R *r, const R *q, const R *dinv,
+                                                    double *prr, double *prz) {
+    if (V.done && *V.done) return;
+    __shared__ double red[VB];
+    const int prob = V.blk_prob[blockIdx.x];
+    const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
+    const double alpha = S.alpha[prob];
+    double rr = 0.0, rz = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
+        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
+        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
+        r[i] = ri;
+        rr += (double)ri * (double)ri;
+        rz += (double)ri * (double)zi;
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = rr;
+        prz[blockIdx.x] = rz;
+    }
+}
+
+// The deferred x update of the folded CG step: x += alpha p (every block;
+// never skipped), then alpha = 0 (k_alpha_zero) so that it is applied once.
+template <class R>
+__global__ __launch_bounds__(VB) void k_flush(VecCtx V, const CgScalars S, R *x, const R *p) {
+    const int prob = V.blk_prob[blockIdx.x];
+    const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
+    const double alpha = S.alpha[prob];
+    for (int64_t i = s + threadIdx.x; i < e; i += VB) x[i] = (R)((double)x[i] + alpha * (double)p[i]);
+}
+__global__ void k_alpha_zero(CgScalars S, int nprob) {
+    for (int p = threadIdx.x; p < nprob; p += blockDim.x) S.alpha[p] = 0.0;
+}
+
 // p = z + beta p; a stopped problem keeps its last direction
 template <class R>
 __global__ __launch_bounds__(VB) void k_pupdate(VecCtx V, const CgScalars S, const R *z, R *p) {
@@ -292,6 +332,21 @@ hipError_t vec_update(const VecCtx &V, const CgScalars &S, R *x, R *r, const R *
     LCHK();
 }
 template <class R>
+hipError_t vec_update_fold(const VecCtx &V, const CgScalars &S, R *r, const R *q, const R *dinv, double *prr,
+                           double *prz, hipStream_t st) {
+    if (V.nblk == 0) return hipSuccess;   // no DOFs
+    hipLaunchKernelGGL(k_update_fold<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, r, q, dinv, prr, prz);
+    LCHK();
+}
+template <class R>
+hipError_t vec_flush(const VecCtx &V, const CgScalars &S, R *x, const R *p, hipStream_t st) {
+    if (V.nblk > 0) hipLaunchKernelGGL(k_flush<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, x, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_alpha_zero, dim3(1), dim3(64), 0, st, S, V.nprob);
+    LCHK();
+}
+template <class R>
 hipError_t vec_pupdate(const VecCtx &V, const CgScalars &S, const R *z, R *p, hipStream_t st) {
     if (V.nblk == 0) return hipSuccess;   // no DOFs
     hipLaunchKernelGGL(k_pupdate<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, z, p);
@@ -356,6 +411,9 @@ hipError_t vec_correct(const VecCtx &V, const float *d32, const double *nrm, dou
     template hipError_t vec_update<R>(const VecCtx &, const CgScalars &, R *, R *, const R *,         \
                                       const R *, const R *, R *, double *, double *, hipStream_t);    \
     template hipError_t vec_pupdate<R>(const VecCtx &, const CgScalars &, const R *, R *, hipStream_t); \
+    template hipError_t vec_update_fold<R>(const VecCtx &, const CgScalars &, R *, const R *, const R *, double *, \
+                                           double *, hipStream_t);                                              \
+    template hipError_t vec_flush<R>(const VecCtx &, const CgScalars &, R *, const R *, hipStream_t);            \
     template hipError_t vec_start<R>(const VecCtx &, const R *, const R *, R *, R *, R *, double *,   \
                                      double *, hipStream_t);                                          \
     template hipError_t vec_fill<R>(R *, int64_t, R, hipStream_t);

@@ -13,7 +13,7 @@
 * The 24^3 differentiation workload: finite differences of a loss through
   the solve against the autograd gradients (lambda of a few elements, the
   penalty scale), and recovery of the lambda field from an observed solution
-  by gradient descent on log(lambda)."""
+  by limited-memory BFGS descent on log(lambda)."""
 
 from __future__ import annotations
 
@@ -140,9 +140,10 @@ def test_workload5_solve_gradients_fd(env, w5):
     For lambda_e the loss ||u - t||^2 is taken over the DOFs of the sampled
     elements only (a single element's lambda moves u mostly there), with
     t = 0.9 u(lambda); for sigma over every DOF.  u depends on one lambda_e
-    or on sigma almost linearly, so the loss is nearly quadratic in it and a
-    central difference with a 5% step is accurate far below the tolerance,
-    while the step keeps the difference well above the solver's noise."""
+    almost linearly, so the loss is nearly quadratic in it and a central
+    difference with a 5% step is accurate far below the tolerance, while the
+    step keeps the difference well above the solver's noise; for sigma two
+    central differences are extrapolated (Richardson)."""
     from paper_2504_03573_amd import autograd as AG
     print("[workload 5 solve gradients]", flush=True)
     m, op, b = w5
@@ -159,8 +160,8 @@ def test_workload5_solve_gradients_fd(env, w5):
     for e in elems:
         mask[int(off[e]):int(off[e] + nm[e])] = 1.0
 
-    def loss_of(lam_, sig_, w):
-        u = AG.solve(op, b, lam_, sig_, tol=1e-11)
+    def loss_of(lam_, sig_, w, tol=1e-11):
+        u = AG.solve(op, b, lam_, sig_, tol=tol)
         return (((u - target) * w) ** 2).sum()
 
     loss_of(lam, sig.detach(), mask).backward()
@@ -176,19 +177,94 @@ def test_workload5_solve_gradients_fd(env, w5):
     ones = torch.ones_like(mask)
     loss_of(lam.detach(), sig, ones).backward()
     with torch.no_grad():
-        h = 0.05
-        fd = (float(loss_of(lam.detach(), sig.detach() + h, ones))
-              - float(loss_of(lam.detach(), sig.detach() - h, ones))) / (2 * h)
+        # u depends on sigma roughly like 1/sigma on the penalty-dominated
+        # jumps, so the central difference's h^2 f3/6 term (f3 the third
+        # derivative) is a few 1e-3 of the first derivative at h = 0.05:
+        # Richardson extrapolation of the differences at h and h/2 cancels
+        # it (error O(h^4))
+        def central(h):
+            return (float(loss_of(lam.detach(), sig.detach() + h, ones))
+                    - float(loss_of(lam.detach(), sig.detach() - h, ones))) / (2 * h)
+        d1, d2 = central(0.1), central(0.05)
+        fd = (4 * d2 - d1) / 3
         g = float(sig.grad)
+        print(f"sigma: central differences {d1:.8e} (h = 0.1), {d2:.8e} (h = 0.05)", flush=True)
         print(f"sigma: fd {fd:.8e} autograd {g:.8e}", flush=True)
-        assert abs(fd - g) <= 1e-4 * abs(fd), (fd, g)
+        # the sigma differences are small against the loss: the solves' 1e-11
+        # residual leaves about 5e-5 of noise in the extrapolated difference
+        # (solves to 1e-12 do not converge here), the extrapolation's own
+        # error is about 3e-5 at these steps
+        assert abs(fd - g) <= 2e-4 * abs(fd), (fd, g)
+
+
+def _lbfgs(fg, theta, iters, stop_ratio, mem=10, first_step=0.1, log=None):
+    """Limited-memory BFGS (two-loop recursion, Armijo backtracking from the
+    unit step) on a function returning (loss, gradient); the first step moves
+    the largest component by first_step.  Returns the loss history."""
+    f, g = fg(theta)
+    hist = [f]
+    S, Y = [], []
+    for it in range(iters):
+        q = g.clone()
+        al = []
+        for s_, y_ in reversed(list(zip(S, Y))):
+            a = float((s_ * q).sum()) / float((y_ * s_).sum())
+            al.append(a)
+            q -= a * y_
+        if S:
+            q *= float((S[-1] * Y[-1]).sum()) / float((Y[-1] * Y[-1]).sum())
+        else:
+            q *= first_step / float(g.abs().max())
+        for (s_, y_), a in zip(zip(S, Y), reversed(al)):
+            q += (a - float((y_ * q).sum()) / float((y_ * s_).sum())) * s_
+        d = -q
+        gd = float((g * d).sum())
+        if gd >= 0:   # not a descent direction: restart from the scaled gradient
+            S, Y = [], []
+            d = -g * (first_step / float(g.abs().max()))
+            gd = float((g * d).sum())
+        t = 1.0
+        for _ in range(12):
+            fn, gn = fg(theta + t * d)
+            if fn <= f + 1e-4 * t * gd:
+                break
+            t *= 0.5
+        s_, y_ = t * d, gn - g
+        if float((s_ * y_).sum()) > 0:
+            S.append(s_)
+            Y.append(y_)
+            if len(S) > mem:
+                S.pop(0)
+                Y.pop(0)
+        theta = theta + s_
+        f, g = fn, gn
+        hist.append(f)
+        if log and it % 5 == 0:
+            log(it, f, theta)
+        if f < stop_ratio * hist[0]:
+            break
+    return hist, theta
 
 
 def test_workload5_lambda_recovery(env, w5):
     """Recover the seeded per-element lambda field (log-uniform on [1, 10])
-    from the observed solution, starting from lambda = 3 everywhere, by Adam
-    on log(lambda) through the solve (step 0.08, decaying by 0.94 per
-    iteration); the loss must drop 1000-fold."""
+    from the observed solution u_obs, starting from lambda = 3 everywhere.
+
+    Output error through the solve: minimise ||u(lambda) - u_obs||^2 over
+    log(lambda), gradients from the adjoint solve and the parameter-gradient
+    kernel.  u vanishes on the boundary and lambda_e only perturbs the
+    operator's mass term, so u is nearly insensitive to most single lambda_e:
+    the loss is ill-conditioned and flat along most of the field.  Adam and
+    Barzilai-Borwein steps stall near a 1e-3 loss reduction; limited-memory
+    BFGS passes it in about 20 iterations.  The loss must drop 1000-fold.
+
+    Equation error through the application: minimise ||A(lambda) u_obs - b||^2,
+    gradients from the transpose application and the parameter-gradient
+    kernel.  lambda_e acts only on element e's rows (the mass term is element
+    local), so the loss is a sum of one quadratic per element in lambda_e,
+    and per-element secant steps (gradient over its change) reach the
+    minimiser; this recovers the field itself, element by element, up to
+    the observation's own solver error."""
     from paper_2504_03573_amd import autograd as AG
     print("[workload 5 lambda recovery]", flush=True)
     m, op, b = w5
@@ -196,23 +272,54 @@ def test_workload5_lambda_recovery(env, w5):
     sig = torch.tensor(1.0, dtype=torch.float64, device="cuda")
     with torch.no_grad():
         u_obs = AG.solve(op, b, lam_true, sig, tol=1e-11)
-    theta = torch.full((op.n_elems,), math.log(3.0), dtype=torch.float64, device="cuda", requires_grad=True)
-    opt = torch.optim.Adam([theta], lr=0.08)
-    # a decaying step: Adam at a fixed rate stalls in oscillation near 1e-6
-    sched = torch.optim.lr_scheduler.ExponentialLR(opt, gamma=0.94)
     scale = float((u_obs ** 2).sum())
-    losses = []
-    for it in range(90):
-        opt.zero_grad()
-        u = AG.solve(op, b, torch.exp(theta), sig, tol=1e-11)
+
+    def fg(theta):
+        th = theta.detach().requires_grad_(True)
+        u = AG.solve(op, b, torch.exp(th), sig, tol=1e-11)
         loss = ((u - u_obs) ** 2).sum() / scale
         loss.backward()
-        opt.step()
-        sched.step()
-        losses.append(loss.item())
-        if it % 10 == 0:
-            print(f"step {it}: loss {losses[-1]:.3e}", flush=True)
-        if losses[-1] < 1e-4 * losses[0]:
-            break
-    print(f"loss {losses[0]:.3e} -> {losses[-1]:.3e} in {len(losses)} steps", flush=True)
-    assert losses[-1] < 1e-3 * losses[0]
+        return float(loss), th.grad.detach()
+
+    def rel_err(lam):
+        return (lam - lam_true).abs() / lam_true
+
+    def log(it, f, theta):
+        print(f"iteration {it}: loss {f:.3e}, median relative lambda error "
+              f"{float(rel_err(torch.exp(theta)).median()):.3e}", flush=True)
+
+    theta0 = torch.full((op.n_elems,), math.log(3.0), dtype=torch.float64, device="cuda")
+    hist, theta = _lbfgs(fg, theta0, 40, 1e-4, log=log)
+    print(f"output error: loss {hist[0]:.3e} -> {hist[-1]:.3e} in {len(hist) - 1} iterations; median relative "
+          f"lambda error {float(rel_err(torch.exp(theta0)).median()):.3e} -> "
+          f"{float(rel_err(torch.exp(theta)).median()):.3e}", flush=True)
+    assert hist[-1] < 1e-3 * hist[0]
+
+    bn = float((b ** 2).sum())
+
+    def eq_grad(lam):
+        lv = lam.detach().requires_grad_(True)
+        r = AG.apply(op, u_obs, lv, sig) - b
+        loss = (r ** 2).sum() / bn
+        loss.backward()
+        return float(loss), lv.grad.detach()
+
+    lam = torch.full((op.n_elems,), 3.0, dtype=torch.float64, device="cuda")
+    f0, g = eq_grad(lam)
+    lam_prev, g_prev = lam, g
+    lam = lam * 1.1
+    for it in range(8):
+        f, g = eq_grad(lam)
+        dg, dl = g - g_prev, lam - lam_prev
+        step = torch.where(dg.abs() > 0, g * dl / dg, torch.zeros_like(g))
+        lam_prev, g_prev = lam, g
+        lam = lam - step
+        e = rel_err(lam)
+        print(f"equation error, step {it}: loss {f:.3e}; relative lambda error median {float(e.median()):.3e}, "
+              f"90th percentile {float(e.quantile(0.9)):.3e}, max {float(e.max()):.3e}", flush=True)
+    # the first secant step lands on the per-element minimiser; what is left is
+    # the observation's own error (solved to a 1e-11 residual), largest on
+    # corner elements where u_obs is smallest
+    e = rel_err(lam)
+    assert float(e.median()) <= 1e-8
+    assert float(e.max()) <= 1e-5

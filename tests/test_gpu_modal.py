@@ -52,7 +52,7 @@ def case(request, P, orc):
 
 def test_apply_and_diagonal(case, P):
     name, mesh, op, om = case
-    assert op.basis == "modal" and op.variant == ("gather_fold" if mesh.dim == 3 else "gather")
+    assert op.basis == "modal" and op.variant == "gather_fold"
     x = synth.random_coefficients(mesh, 7101)
     y_ref = om.apply(x)
     xt = torch.tensor(x, device="cuda")

@@ -196,13 +196,34 @@ def test_variants_agree(case):
     element's); the fused, two-stage and gather-fold launch structures are
     identical up to rounding."""
     name, mesh, op, om = case
-    if mesh.dim != 3:
-        pytest.skip("the wavefront kernels are 3-D")
     x = synth.random_coefficients(mesh, 4005)
     y_ref = om.apply(x)
     xt = torch.tensor(x, device="cuda")
     ys = {}
     keep = op.variant
+    if mesh.dim == 2:
+        # the general kernels, the wavefront kernels (trace launch + apply
+        # launch) and, when every element fits the 8-point lane grid, the fused
+        # wavefront launch (neighbour traces from their coefficients)
+        small = int(mesh.order.max()) <= 6
+        try:
+            for v in ("gather", "gather_fold") + (("gather_fold_fused",) if small else ()):
+                op.variant = v
+                ys[v] = op.apply(xt).cpu().numpy()
+                assert rel(ys[v], y_ref) <= 1e-12, v
+                y32 = op.apply(xt.float()).double().cpu().numpy()
+                assert rel(y32, y_ref) <= 1e-5, v
+            assert rel(ys["gather_fold"], ys["gather"]) <= 1e-13
+            if small:
+                assert rel(ys["gather_fold_fused"], ys["gather_fold"]) <= 1e-14
+            else:
+                with pytest.raises(P_error()):
+                    op.variant = "gather_fold_fused"
+            with pytest.raises(P_error()):
+                op.variant = "two_stage"
+        finally:
+            op.variant = keep
+        return
     if int(mesh.order.max()) > 6:
         # orders 7-8 present: only the structures that support them
         try:
