@@ -189,12 +189,14 @@ __global__ void k_points(const double *corners, const int *order, const FaceRef 
 //    eq. IP with the neighbour's coefficients zero; boundary faces by the
 //    mirrored value, twice the consistency and penalty terms).
 // The operation count is O(n^{d+1}) per term instead of O(n^d N_P^d).
-template <int DIM>
-__global__ __launch_bounds__(256) void k_diag(const int *order, const int64_t *xoff, const int64_t *voff,
+// One launch per order group (elems: the group's element ids), LDS sized for
+// the group's order.
+template <int DIM, int P>
+__global__ __launch_bounds__(256) void k_diag(const int *elems, const int64_t *xoff, const int64_t *voff,
                                               const FaceRef *eface, const int64_t *foff, const double *vgeo,
                                               const double *fgeo, const double *lam, const double *tau,
                                               const double *tab, double *diag) {
-    constexpr int S = PMAX + 1, NM3 = DIM == 3 ? NMAX * NMAX * NMAX : NMAX * NMAX;
+    constexpr int S = PMAX + 1, NM3 = DIM == 3 ? (P + 2) * (P + 2) * (P + 2) : (P + 2) * (P + 2);
     constexpr int NG = DIM * (DIM + 1) / 2 + 1;
     __shared__ double T[3][NMAX * S];   // B^2, D^2, B D at the volume points [q][i]
     __shared__ double G[NM3];           // one geometric factor at the volume points
@@ -204,9 +206,9 @@ __global__ __launch_bounds__(256) void k_diag(const int *order, const int64_t *x
     __shared__ double FW[4][NMAX * NMAX];   // a, C_k, C_a, C_b at (t1, t2)
     __shared__ double Y[3][NMAX * S];   // first face contraction [t2][i_a]
     __shared__ double SV[2][S * S];     // S_vv, S_vd [i_b][i_a]
-    const int64_t e = blockIdx.x;
+    const int64_t e = elems[blockIdx.x];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int P = order[e], n = P + 2, np = P + 1;
+    constexpr int n = P + 2, np = P + 1;
     const int nm = DIM == 3 ? np * np * np : np * np;
     const int npts = DIM == 3 ? n * n * n : n * n;
     const double *Bn = tab + tab_off_BF(n), *Dn = tab + tab_off_DBF(n);
@@ -445,13 +447,26 @@ hipError_t launch_points(int dim, int64_t ne, const double *corners, const int *
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int dim, int64_t ne, const int *order, const int64_t *xoff,
+hipError_t launch_diag(int dim, int P, int64_t count, const int *elems, const int64_t *xoff,
                        const int64_t *voff, const FaceRef *eface, const int64_t *foff,
                        const double *vgeo, const double *fgeo, const double *lam,
                        const double *tau, const double *tab, double *diag, hipStream_t st) {
-    if (ne == 0) return hipSuccess;
-    if (dim == 2) hipLaunchKernelGGL(k_diag<2>, dim3(ne), dim3(128), 0, st, order, xoff, voff, eface, foff, vgeo, fgeo, lam, tau, tab, diag);
-    else hipLaunchKernelGGL(k_diag<3>, dim3(ne), dim3(256), 0, st, order, xoff, voff, eface, foff, vgeo, fgeo, lam, tau, tab, diag);
+    if (count == 0) return hipSuccess;
+#define SIPDG_DIAG_CASE(PP)                                                                                      \
+    case PP:                                                                                                    \
+        if (dim == 2)                                                                                           \
+            hipLaunchKernelGGL((k_diag<2, PP>), dim3(count), dim3(128), 0, st, elems, xoff, voff, eface, foff, \
+                               vgeo, fgeo, lam, tau, tab, diag);                                                \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_diag<3, PP>), dim3(count), dim3(256), 0, st, elems, xoff, voff, eface, foff, \
+                               vgeo, fgeo, lam, tau, tab, diag);                                                \
+        break;
+    switch (P) {
+        SIPDG_DIAG_CASE(1) SIPDG_DIAG_CASE(2) SIPDG_DIAG_CASE(3) SIPDG_DIAG_CASE(4)
+        SIPDG_DIAG_CASE(5) SIPDG_DIAG_CASE(6) SIPDG_DIAG_CASE(7) SIPDG_DIAG_CASE(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef SIPDG_DIAG_CASE
     return hipGetLastError();
 }
 

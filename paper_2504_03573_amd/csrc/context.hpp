@@ -96,6 +96,7 @@ struct LaunchRec {
 
 struct CgWork;  // defined in the solver
 struct FaceTopo;
+struct NbDesc2;
 
 }  // namespace sipdg
 
@@ -173,6 +174,7 @@ struct sipdg_ctx {
     // points, by decreasing order (ElemDesc::pad = order), four faces each
     sipdg::ElemDesc *d_w2desc = nullptr;
     sipdg::FaceDesc *d_w2fdesc = nullptr;
+    sipdg::NbDesc2 *d_w2nb = nullptr;
     int w2count = 0;
     int *d_eprob = nullptr;   // [n_elems] problem of each element
     int num_cu = 256;

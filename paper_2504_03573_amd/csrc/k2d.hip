@@ -91,7 +91,7 @@ __device__ __forceinline__ void elem2(const Args2 &A, const Data2<R> &D, int i, 
     R tau = 0;
     int nf = 0, slot = 2;
     if (fl) {
-        fr = A.fdesc[(int64_t)i * 4 + f];
+        fr = A.fdesc[(int64_t)i * 4 + f];   // with the neighbour record below: one round of loads
         nf = face_nf(fr.info);
         slot = face_slot(fr.info);
         if (MODE != M_TRACE) tau = D.tau[fr.F];
@@ -100,15 +100,13 @@ __device__ __forceinline__ void elem2(const Args2 &A, const Data2<R> &D, int i, 
     // face and orientation relative to the owner's point order
     int npn = 0, kn = 0, sn = 0, on = 0;
     int64_t xn = 0;
-    if (MODE == M_FUSED && fl && slot != 2) {
-        const FaceTopo ft = A.faces[fr.F];
-        const int nb = slot == 0 ? ft.eR : ft.eL;
-        const int fn = slot == 0 ? ft.fR : ft.fL;
-        on = slot == 0 ? ft.orient : 0;
-        kn = fn >> 1;
-        sn = fn & 1;
-        npn = A.order[nb] + 1;
-        xn = A.xoff[nb];
+    if (MODE == M_FUSED && fl) {
+        const NbDesc2 nd = A.nbdesc[(int64_t)i * 4 + f];
+        npn = nd.code & 15;
+        kn = (nd.code >> 5) & 1;
+        sn = (nd.code >> 4) & 1;
+        on = nd.code >> 6;
+        xn = nd.xn;
     }
 
     // coefficients and tables into LDS

@@ -48,13 +48,18 @@ struct FaceTopo {
 
 // 2-D wavefront kernels (k2d.hip): every quadrilateral of order <= 6 whose
 // faces carry at most 8 trace points, one wavefront each, one launch.
+// The neighbour across one face of a 2-D wavefront element (fused mode):
+// its coefficient offset, and code = N_P | local face << 4 | orientation
+// relative to the owner's point order << 6 (0 on boundary faces).
+struct NbDesc2 {
+    int64_t xn;
+    int code, pad;
+};
 struct Args2 {
     const ElemDesc *desc;    // [count], by decreasing order; pad: order
     const FaceDesc *fdesc;   // [count][4]
+    const NbDesc2 *nbdesc;   // [count][4]
     int count;
-    const FaceTopo *faces;   // [n_faces] (neighbour lookup of the fused mode)
-    const int *order;        // [n_elems]
-    const int64_t *xoff;     // [n_elems]
     const int *skip;         // stop flag of a captured solver loop, or null
 };
 template <class R>
@@ -81,7 +86,8 @@ hipError_t launch_geo_faces(int dim, int64_t nfaces, const double *corners, cons
 hipError_t launch_points(int dim, int64_t ne, const double *corners, const int *order,
                          const FaceRef *eface, const int64_t *qoff, const int64_t *boff,
                          const double *tab, double *xq, double *xb, hipStream_t st);
-hipError_t launch_diag(int dim, int64_t ne, const int *order, const int64_t *xoff,
+// Jacobi diagonal of one order group (elems: its element ids)
+hipError_t launch_diag(int dim, int P, int64_t count, const int *elems, const int64_t *xoff,
                        const int64_t *voff, const FaceRef *eface, const int64_t *foff,
                        const double *vgeo, const double *fgeo, const double *lam,
                        const double *tau, const double *tab, double *diag, hipStream_t st);

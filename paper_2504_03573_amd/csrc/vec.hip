@@ -114,10 +114,47 @@ __global__ __launch_bounds__(VB) void k_pupdate(VecCtx V, const CgScalars S, con
 
 // Sum of part[b0, b1) by the whole block in a fixed order: thread t adds
 // b0 + t, b0 + t + VB, ..., then the fixed tree of block_sum.
-__device__ inline double seg_sum(const double *part, int b0, int b1, double *red) {
+//
+// The partials are loaded 8 per thread at a time before they are added (in
+// the same order), so a thread waits on one round of loads per 8 values
+// instead of one per value.
+constexpr int SEG_BATCH = 8;
+__device__ inline double seg_acc(const double *part, int b0, int b1) {
     double acc = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += VB) acc += part[b];
-    return block_sum(acc, red);
+    for (int b = b0 + threadIdx.x; b < b1; b += SEG_BATCH * VB) {
+        double v[SEG_BATCH];
+#pragma unroll
+        for (int j = 0; j < SEG_BATCH; ++j) v[j] = b + j * VB < b1 ? part[b + j * VB] : 0.0;
+#pragma unroll
+        for (int j = 0; j < SEG_BATCH; ++j)
+            if (b + j * VB < b1) acc += v[j];
+    }
+    return acc;
+}
+__device__ inline double seg_sum(const double *part, int b0, int b1, double *red) {
+    return block_sum(seg_acc(part, b0, b1), red);
+}
+// Two segmented sums over the same range, with the loads of both in flight
+// together.
+__device__ inline void seg_sum2(const double *pa, const double *pb, int b0, int b1, double *red, double &sa,
+                                double &sb) {
+    double aa = 0.0, ab = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += SEG_BATCH * VB) {
+        double va[SEG_BATCH], vb[SEG_BATCH];
+#pragma unroll
+        for (int j = 0; j < SEG_BATCH; ++j) {
+            va[j] = b + j * VB < b1 ? pa[b + j * VB] : 0.0;
+            vb[j] = b + j * VB < b1 ? pb[b + j * VB] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < SEG_BATCH; ++j)
+            if (b + j * VB < b1) {
+                aa += va[j];
+                ab += vb[j];
+            }
+    }
+    sa = block_sum(aa, red);
+    sb = block_sum(ab, red);
 }
 
 // Batch-wide vote of the per-problem blocks of a finalisation launch (thread
@@ -161,8 +198,7 @@ __global__ __launch_bounds__(VB) void k_fin_beta(VecCtx V, CgScalars S, const do
     const bool run = S.conv[p] == 0;   // the same on every thread
     double rr = 0.0, rz = 0.0;
     if (run) {
-        rr = seg_sum(prr, V.prob_blk[p], V.prob_blk[p + 1], red);
-        rz = seg_sum(prz, V.prob_blk[p], V.prob_blk[p + 1], red);
+        seg_sum2(prr, prz, V.prob_blk[p], V.prob_blk[p + 1], red, rr, rz);
     }
     if (threadIdx.x != 0) return;
     bool active = false;
@@ -219,8 +255,8 @@ __global__ __launch_bounds__(VB) void k_fin_start(VecCtx V, CgScalars S, const d
                                                    const double *bnorm_src, const int *preconv, double tol) {
     __shared__ double red[VB];
     const int p = blockIdx.x;
-    const double rr = seg_sum(prr, V.prob_blk[p], V.prob_blk[p + 1], red);
-    const double rz = seg_sum(prz, V.prob_blk[p], V.prob_blk[p + 1], red);
+    double rr, rz;
+    seg_sum2(prr, prz, V.prob_blk[p], V.prob_blk[p + 1], red, rr, rz);
     if (threadIdx.x != 0) return;
     const double bn = bnorm_src ? bnorm_src[p] : sqrt(rr);
     S.bnorm[p] = bn;
@@ -250,8 +286,8 @@ __global__ __launch_bounds__(VB) void k_fin_cont(VecCtx V, CgScalars S, const do
                                                   const int *preconv, const double *ratio, double tol) {
     __shared__ double red[VB];
     const int p = blockIdx.x;
-    const double rr = seg_sum(prr, V.prob_blk[p], V.prob_blk[p + 1], red);
-    const double rz = seg_sum(prz, V.prob_blk[p], V.prob_blk[p + 1], red);
+    double rr, rz;
+    seg_sum2(prr, prz, V.prob_blk[p], V.prob_blk[p + 1], red, rr, rz);
     if (threadIdx.x != 0) return;
     const double bn = sqrt(rr);
     const double rho = S.rho[p];
