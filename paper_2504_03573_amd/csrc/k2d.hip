@@ -54,16 +54,31 @@ enum {
 // u, d_k u and d_a u at trace point t of an element's face normal to k at
 // side s: x has np modes per direction (first direction fastest), n the
 // element's GLL points, nf the trace points.
-template <class R>
+// np <= NPM: the table entries are loaded into registers first (one round
+// of loads), then the sums run fully unrolled over NPM with np guarding.
+template <class R, int NPM>
 __device__ __forceinline__ void face_eval(const R *x, int np, int n, int k, int s, const R *tab, int nf, int t,
                                           R &u, R &dk, R &da) {
     const int end = s ? n - 1 : 0;
-    const R *E = tab + tab_off_BF(n) + end * S9, *Ed = tab + tab_off_DBF(n) + end * S9;
-    const R *F = tab + tab_off_BF(nf) + t * S9, *Fd = tab + tab_off_DBF(nf) + t * S9;
+    const R *Ep = tab + tab_off_BF(n) + end * S9, *Edp = tab + tab_off_DBF(n) + end * S9;
+    const R *Fp = tab + tab_off_BF(nf) + t * S9, *Fdp = tab + tab_off_DBF(nf) + t * S9;
+    R E[NPM], Ed[NPM], F[NPM], Fd[NPM];
+#pragma unroll
+    for (int i = 0; i < NPM; ++i) {
+        const bool ok = i < np;
+        E[i] = ok ? Ep[i] : R(0);
+        Ed[i] = ok ? Edp[i] : R(0);
+        F[i] = ok ? Fp[i] : R(0);
+        Fd[i] = ok ? Fdp[i] : R(0);
+    }
     u = dk = da = R(0);
-    for (int ia = 0; ia < np; ++ia) {
+#pragma unroll
+    for (int ia = 0; ia < NPM; ++ia) {
+        if (ia >= np) break;
         R r0 = 0, r1 = 0;
-        for (int ik = 0; ik < np; ++ik) {
+#pragma unroll
+        for (int ik = 0; ik < NPM; ++ik) {
+            if (ik >= np) break;
             const R xv = x[k == 0 ? ik + np * ia : ia + np * ik];
             r0 += xv * E[ik];
             r1 += xv * Ed[ik];
@@ -140,7 +155,7 @@ __device__ __forceinline__ void elem2(const Args2 &A, const Data2<R> &D, int i, 
         const R *Co = fg + nf * (1 + 2 * gs) + qc;
         const R Ck = Co[k * nf], Ca = Co[a * nf];
         R ou, odk, oda;
-        face_eval<R>(XS, NP, N, k, s, D.tab, nf, t, ou, odk, oda);
+        face_eval<R, NP>(XS, NP, N, k, s, D.tab, nf, t, ou, odk, oda);
         const R og = Ck * odk + Ca * oda;
         const int so = slot == 1 ? 1 : 0;
         if (MODE == M_TRACE) {
@@ -159,7 +174,7 @@ __device__ __forceinline__ void elem2(const Args2 &A, const Data2<R> &D, int i, 
             } else {
                 const int tn = (on & 1) ? nf - 1 - qc : qc;
                 R ndk, nda;
-                face_eval<R>(NX + f * 64, npn, npn + 1, kn, sn, D.tab, nf, tn, nu, ndk, nda);
+                face_eval<R, 7>(NX + f * 64, npn, npn + 1, kn, sn, D.tab, nf, tn, nu, ndk, nda);
                 const R *Cn = fg + nf * (1 + 2 * (1 - gs)) + qc;
                 ng = Cn[kn * nf] * ndk + Cn[(1 - kn) * nf] * nda;
             }
@@ -199,12 +214,16 @@ __device__ __forceinline__ void elem2(const Args2 &A, const Data2<R> &D, int i, 
             lb[16] = fb[16 + t];
         } else {
             const R *I = D.tab + tab_off_I(N, nf);
+            R wv[NFM];
+#pragma unroll
+            for (int tt = 0; tt < NFM; ++tt) wv[tt] = tt < nf ? I[tt * N + t] : R(0);
             R c0 = 0, c1 = 0, c2 = 0;
-            for (int tt = 0; tt < nf; ++tt) {
-                const R w = I[tt * N + t];
-                c0 += w * fb[tt];
-                c1 += w * fb[8 + tt];
-                c2 += w * fb[16 + tt];
+#pragma unroll
+            for (int tt = 0; tt < NFM; ++tt) {
+                if (tt >= nf) break;
+                c0 += wv[tt] * fb[tt];
+                c1 += wv[tt] * fb[8 + tt];
+                c2 += wv[tt] * fb[16 + tt];
             }
             lb[0] = c0;
             lb[8] = c1;
