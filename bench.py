@@ -259,6 +259,94 @@ def bench_2d(args, stream):
     return res
 
 
+def _lam_points(m):
+    """lambda of the element owning each volume quadrature point (points
+    element after element, (p+2)^d per element)."""
+    import numpy as np
+    npts = (m.order.astype(np.int64) + 2) ** m.dim
+    return np.repeat(np.broadcast_to(np.asarray(m.lam, dtype=np.float64), (m.n_elems,)), npts)
+
+
+def bench_batched(args, stream):
+    """The 64-problem batch (problem i: n_i^3 perturbed hexes, order p_i,
+    lambda_i; one handle, every order group of all problems in one launch):
+    FP64 and FP32 application after autotuning, and Jacobi-PCG to 1e-10 of
+    every problem (FP64, FP32 inside FP64 refinement) on the manufactured
+    sin(pi x) sin(pi y) sin(pi z) problems."""
+    import torch
+
+    import synth
+    from paper_2504_03573_amd import SipdgOperator, inspect_mesh
+    meshes = synth.workload(4)
+    op = SipdgOperator.batch(meshes)
+    tuned = op.autotune(10)
+    x = torch.randn(op.n_dofs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    x32, y32 = x.float(), torch.empty(op.n_dofs, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        op.apply(x, out=y)
+        op.apply(x32, out=y32)
+    reps = max(10, min(args.steps, 50))
+    ms = time_events(lambda: op.apply(x, out=y), reps, stream)
+    ms32 = time_events(lambda: op.apply(x32, out=y32), reps, stream)
+    lam_q = torch.cat([torch.tensor(_lam_points(m), device="cuda") for m in meshes])
+
+    def src(X):
+        v = torch.sin(math.pi * X[:, 0]) * torch.sin(math.pi * X[:, 1]) * torch.sin(math.pi * X[:, 2])
+        return (lam_q + 3 * math.pi ** 2) * v
+    b = op.rhs(src, _zero)
+    b64 = sum(algorithmic_bytes(inspect_mesh(m), 3, 8) for m in meshes)
+    b32 = sum(algorithmic_bytes(inspect_mesh(m), 3, 4) for m in meshes)
+    cg = {}
+    for mode in ("f64", "f32_ir"):
+        op.cg_solve(b, tol=1e-10, mode=mode, maxit=50, raise_on_fail=False)
+        torch.cuda.synchronize()
+        _, info = op.cg_solve(b, tol=1e-10, mode=mode, maxit=getattr(args, "cg_iters", 100000), raise_on_fail=False)
+        cg[mode] = solve_record(info, op.n_dofs, b64 if mode == "f64" else b32, 8 if mode == "f64" else 4)
+    res = {"workload": synth.WORKLOADS[4], "problems": len(meshes), "n_dofs": op.n_dofs, "variant": op.variant,
+           "autotune_ms": tuned, "apply_ms": ms, "gdofs": op.n_dofs / (ms * 1e-3) / 1e9,
+           "roofline_frac": b64 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "apply_fp32_ms": ms32, "gdofs_fp32": op.n_dofs / (ms32 * 1e-3) / 1e9, "cg": cg}
+    op.close()
+    return res
+
+
+def bench_workload5(args, stream):
+    """The 24^3 differentiation workload (orders 3..5, per-element lambda):
+    the FP64 application, its transpose, the parameter gradients (the
+    backward of the autograd application) and the FP64 PCG solve."""
+    import torch
+
+    import synth
+    from paper_2504_03573_amd import SipdgOperator, inspect_mesh
+    m = synth.workload(5)
+    op = SipdgOperator(m)
+    op.autotune(20)
+    x = torch.tensor(synth.random_coefficients(m, 4005), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        op.apply(x, out=y)
+    reps = max(20, min(args.steps, 100))
+    ms = time_events(lambda: op.apply(x, out=y), reps, stream)
+    mst = time_events(lambda: op.apply_transpose(x, out=y), reps, stream)
+    msg = time_events(lambda: op.param_grad(x, y), reps, stream)
+    lam_q = torch.tensor(_lam_points(m), device="cuda")
+
+    def src(X):
+        v = torch.sin(math.pi * X[:, 0]) * torch.sin(math.pi * X[:, 1]) * torch.sin(math.pi * X[:, 2])
+        return (lam_q + 3 * math.pi ** 2) * v
+    b = op.rhs(src, _zero)
+    op.cg_solve(b, tol=1e-10, maxit=50, raise_on_fail=False)
+    torch.cuda.synchronize()
+    _, info = op.cg_solve(b, tol=1e-10, maxit=getattr(args, "cg_iters", 100000), raise_on_fail=False)
+    res = {"workload": synth.WORKLOADS[5], "n_dofs": op.n_dofs, "variant": op.variant,
+           "apply_us": ms * 1e3, "gdofs": op.n_dofs / (ms * 1e-3) / 1e9, "apply_transpose_us": mst * 1e3,
+           "param_grad_us": msg * 1e3,
+           "cg_f64": solve_record(info, op.n_dofs, algorithmic_bytes(inspect_mesh(m), 3, 8), 8)}
+    op.close()
+    return res
+
+
 def bench_sweep(stream, reps=30):
     """FP64 application throughput against problem size and order (the
     paper's size study, Sec. 5.2): perturbed hex meshes N^3 with one order p
@@ -372,6 +460,8 @@ def main():
                     help="skip the 2-D workloads (4^2 p=3 and 64^2 checkerboard 4/5)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the throughput sweep over problem size and order")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-problem batch and the 24^3 differentiation workload")
     ap.add_argument("--cg-iters", type=int, default=100000,
                     help="iteration cap of every CG solve (profiling runs: a bounded number of iterations; "
                          "solves that stop at the cap report converged false)")
@@ -604,6 +694,9 @@ def main():
         op.variant = keep
     if not args.no_2d:
         out["workloads_2d"] = bench_2d(args, stream)
+    if not args.no_batch:
+        out["workload_4_batched"] = bench_batched(args, stream)
+        out["workload_5"] = bench_workload5(args, stream)
     if not args.no_sweep:
         out["sweep"] = bench_sweep(stream)
     if not args.no_cpu:
