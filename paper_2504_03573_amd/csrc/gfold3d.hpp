@@ -856,6 +856,17 @@ enum : int {
     GEO_MAP = 2,      // from the element's trilinear map, at every point
 };
 
+// Points per batch of stored-factor loads in the pointwise terms (7 values
+// per point), per order: as many as fit the register budget of the launch's
+// occupancy (FP64 orders 3 and 4 stay at 3 waves per SIMD with 3 and 2 points
+// per batch, order 5 only with 1; the 2-wave order 6 takes 4).  FP32 loads a
+// whole column at once.
+template <class R, int P>
+struct PwBatch {
+    static constexpr int N = P + 2;
+    static constexpr int V = sizeof(R) == 4 ? N : (P <= 2 ? N : P == 3 ? 3 : P == 4 ? 2 : P == 6 ? 4 : 1);
+};
+
 // Pointwise terms of one column (q0, q1) = (a, b), in place:
 // u <- lambda w |J| u, d <- (w G~) d with d the reference gradient.
 // GEO_POINT reads the stored per-point factors, in chunks, so that the loads
@@ -940,20 +951,35 @@ __device__ __forceinline__ void pointwise(const Data<R> &D, const ElemDesc &ed, 
         }
         return;
     }
-    const R *__restrict__ vg = D.vgeo + ed.voff;
+    const R *__restrict__ vg = D.vgeo + ed.voff + a + N * b;
     const R lam = D.lam[e];
+    // QB points' factors are loaded before any of them is used (one memory
+    // round trip per batch instead of one per point); the scheduling barrier
+    // keeps the compiler from interleaving loads and uses again.
+    constexpr int QB = PwBatch<R, P>::V;
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-        const int p = a + N * (b + N * q);
-        const R g00 = vg[p], g01 = vg[NPTS + p], g02 = vg[2 * NPTS + p];
-        const R g11 = vg[3 * NPTS + p], g12 = vg[4 * NPTS + p], g22 = vg[5 * NPTS + p];
-        const R wj = vg[6 * NPTS + p];
-        const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
-        u[q] = lam * wj * u[q];
-        d0[q] = g00 * c0 + g01 * c1 + g02 * c2;
-        d1[q] = g01 * c0 + g11 * c1 + g12 * c2;
-        d2[q] = g02 * c0 + g12 * c1 + g22 * c2;
-        if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    for (int q0 = 0; q0 < N; q0 += QB) {
+        R g[QB][7];
+#pragma unroll
+        for (int j = 0; j < QB; ++j) {
+            if (q0 + j < N) {
+#pragma unroll
+                for (int f = 0; f < 7; ++f) g[j][f] = vg[f * NPTS + N * N * (q0 + j)];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < QB; ++j) {
+            const int q = q0 + j;
+            if (q < N) {
+                const R c0 = d0[q], c1 = d1[q], c2 = d2[q];
+                u[q] = lam * g[j][6] * u[q];
+                d0[q] = g[j][0] * c0 + g[j][1] * c1 + g[j][2] * c2;
+                d1[q] = g[j][1] * c0 + g[j][3] * c1 + g[j][4] * c2;
+                d2[q] = g[j][2] * c0 + g[j][4] * c1 + g[j][5] * c2;
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -983,15 +1009,28 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     const ctab<R> Bt = as_const(D.tab) + tab_off_B(P);   // [N][NP]
     const ctab<R> Dt = as_const(D.tab) + tab_off_D(N);   // [N][N]
     const int64_t xo = ed.xoff;
-    const MetaV<R> meta = load_meta<R, MODE>(A, D, blk);
-    // interpolation tables of this order into LDS (read after several syncs)
-    R *itl = SA + S::TOTAL;
-    if constexpr (MODE != 3) {
+    // Prologue: the first line contraction's coefficients, the face
+    // descriptors and the interpolation tables are all requested before any
+    // of them is waited for (one memory round trip instead of a chain).
+    constexpr bool XEARLY = MODE != 3;
+    R xv[NP];
+    if (XEARLY && a < NP && b < NP) {
+        const R *__restrict__ xe = D.x + xo + NP * (a + NP * b);
 #pragma unroll
-        for (int m = N + 1; m <= Geo<P>::NFMAX; ++m) {
-            const R *__restrict__ src = D.tab + tab_off_I(N, m);
-            for (int i = l; i < m * N; i += WG) itl[itab_off<P>(m) + i] = src[i];
-        }
+        for (int i = 0; i < NP; ++i) xv[i] = xe[i];
+    }
+    const MetaV<R> meta = load_meta<R, MODE>(A, D, blk);
+    // interpolation tables I(n, m) of this order for m = n+1 .. the largest
+    // trace: m n <= W entries each, one per lane, stored to LDS after the
+    // first contraction (read after several syncs)
+    R *itl = SA + S::TOTAL;
+    constexpr int NIT = (MODE != 3 && Geo<P>::NFMAX > N) ? Geo<P>::NFMAX - N : 0;
+    static_assert(Geo<P>::NFMAX * N <= WG || NIT == 0, "one table entry per lane");
+    R itv[NIT > 0 ? NIT : 1];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int m = N + 1 + j;
+        itv[j] = l < m * N ? D.tab[tab_off_I(N, m) + l] : R(0);
     }
     // Gauss volume points: the faces' terms of every mode first (the point
     // arrays serve as scratch), kept after them
@@ -1016,17 +1055,23 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
 
     // BwdTrans along xi_0: lane (i1, i2)
     if (a < NP && b < NP) {
-        const R *__restrict__ xe = D.x + xo + NP * (a + NP * b);
-        R v[NP];
+        if constexpr (!XEARLY) {
+            const R *__restrict__ xe = D.x + xo + NP * (a + NP * b);
 #pragma unroll
-        for (int i = 0; i < NP; ++i) v[i] = xe[i];
+            for (int i = 0; i < NP; ++i) xv[i] = xe[i];
+        }
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             R s = 0;
 #pragma unroll
-            for (int i = 0; i < NP; ++i) s += Bt[q * NP + i] * v[i];
+            for (int i = 0; i < NP; ++i) s += Bt[q * NP + i] * xv[i];
             SA[pa<P>(q, a, b)] = s;
         }
+    }
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int m = N + 1 + j;
+        if (l < m * N) itl[itab_off<P>(m) + l] = itv[j];
     }
     __syncthreads();
     // along xi_1: lane (q0, i2)
