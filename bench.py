@@ -448,6 +448,9 @@ def main():
                     help="kept for the profiling commands (the 1 GiB copy always runs)")
     ap.add_argument("--variant", default=None,
                     help="kernel structure to use instead of the autotuner's choice (profiling runs)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner on the 32^3 workload: default tile shapes (profiling runs, where "
+                         "counter collection distorts its timing)")
     ap.add_argument("--no-modal", action="store_true",
                     help="skip the apply in the modified C0 modal basis")
     ap.add_argument("--no-gauss", action="store_true",
@@ -481,7 +484,7 @@ def main():
     mesh = synth.workload(WORKLOAD)
     st = inspect_mesh(mesh)
     op = SipdgOperator(mesh)
-    tuned = op.autotune(20)
+    tuned = None if args.no_autotune else op.autotune(20)
     if args.variant:
         # profiling runs pin the kernel structure (counters distort the autotuner's timing)
         op.variant = args.variant
