@@ -1727,28 +1727,40 @@ int sipdg_autotune(sipdg_handle h, const char *cache_path, int reps, double *ms_
             h->blocks_per_cu = vshape;
         } else if (v == SIPDG_VARIANT_GATHER_FOLD && h->dim == 3) {
             // tile shape of each order group's apply launch, one order at a
-            // time (the others fixed at their best so far)
+            // time (the others fixed at their best so far).  Each candidate
+            // is timed in alternation with the incumbent shape, twice each,
+            // and the faster run of each kept, so that a slow early run or a
+            // drifting clock does not favour the shape timed later; it must
+            // win by more than the timing noise (2 %), so that runs of the
+            // same build keep the same shapes unless one clearly wins.
             rc = time_apply(vbest);
             for (int P = 1; P <= SIPDG_MAX_ORDER && rc == SIPDG_OK; ++P) {
                 bool present = false;
                 for (const Group &g : h->groups) present |= g.P == P && g.count > 0;
                 if (!present) continue;
-                const int t0 = h->tile[P], b0 = h->budget[P];
-                int bt = t0, bb = b0;
+                int bt = h->tile[P], bb = h->budget[P];
                 for (const TileShape &ts : tile_shapes(P)) {
-                    if (ts.tile == t0 && ts.budget == b0) continue;
-                    h->tile[P] = ts.tile;
-                    h->budget[P] = ts.budget;
-                    double t = 0.0;
-                    rc = time_apply(t);
+                    if (ts.tile == bt && ts.budget == bb) continue;
+                    double ti = 1e300, tc = 1e300;
+                    for (int k = 0; k < 2 && rc == SIPDG_OK; ++k) {
+                        double t = 0.0;
+                        h->tile[P] = bt;
+                        h->budget[P] = bb;
+                        rc = time_apply(t);
+                        ti = std::min(ti, t);
+                        if (rc != SIPDG_OK) break;
+                        h->tile[P] = ts.tile;
+                        h->budget[P] = ts.budget;
+                        rc = time_apply(t);
+                        tc = std::min(tc, t);
+                    }
                     if (rc != SIPDG_OK) break;
-                    // a shape must beat the best so far by more than the
-                    // timing noise (2 %), so that runs of the same build
-                    // keep the same shapes unless one clearly wins
-                    if (t < 0.98 * vbest) {
-                        vbest = t;
+                    if (tc < 0.98 * ti) {
                         bt = ts.tile;
                         bb = ts.budget;
+                        vbest = tc;
+                    } else {
+                        vbest = std::min(vbest, ti);
                     }
                 }
                 h->tile[P] = bt;
