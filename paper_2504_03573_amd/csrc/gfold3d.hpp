@@ -84,12 +84,15 @@ struct Sz {
     // Every trace of this order has the element's own n points (n = NFMAX):
     // the apply takes its own (u, g) from its face values instead of the trace
     // buffer, and keeps the fields of the faces normal to xi_1 and xi_2 until
-    // their phase in OWN_STASH = [16][W] after the point arrays (each lane
-    // reads back only its own entries; the face scratch beyond FB is unused,
-    // since no face interpolates).
+    // their phase in OWN_STASH = [16][W] at 8 W, past the lifted-flux array FB
+    // (each lane reads back only its own entries).  The stash takes the place
+    // of the face scratch, which no face of this order uses (none
+    // interpolates), and of the point arrays, which are dead from the end of
+    // the gradient phase until the inner product.
     static constexpr bool OWN = N == Geo<P>::NFMAX;
-    static constexpr int STASH = OWN ? 16 * Geo<P>::W : 0;
-    static constexpr int TOTAL = 2 * ARR + STASH > SCR ? 2 * ARR + STASH : SCR;
+    static constexpr int STASH_OFF = 8 * Geo<P>::W;
+    static_assert(!OWN || STASH_OFF + 16 * Geo<P>::W <= SCR, "the stash must fit the face scratch");
+    static constexpr int TOTAL = 2 * ARR > SCR ? 2 * ARR : SCR;
 };
 
 // face scratch (R units from the block's LDS base, W = Geo<P>::W):
@@ -858,13 +861,12 @@ enum : int {
 
 // Points per batch of stored-factor loads in the pointwise terms (7 values
 // per point), per order: as many as fit the register budget of the launch's
-// occupancy (FP64 orders 3 and 4 stay at 3 waves per SIMD with 3 and 2 points
-// per batch, order 5 only with 1; the 2-wave order 6 takes 4).  FP32 loads a
-// whole column at once.
+// occupancy (FP64 orders 3, 4 and 6 stay at 3 waves per SIMD with 3, 2 and 2
+// points per batch, order 5 only with 1).  FP32 loads a whole column at once.
 template <class R, int P>
 struct PwBatch {
     static constexpr int N = P + 2;
-    static constexpr int V = sizeof(R) == 4 ? N : (P <= 2 ? N : P == 3 ? 3 : P == 4 ? 2 : P == 6 ? 4 : 1);
+    static constexpr int V = sizeof(R) == 4 ? N : (P <= 2 ? N : P == 3 ? 3 : P == 4 ? 2 : P == 6 ? 2 : 1);
 };
 
 // Pointwise terms of one column (q0, q1) = (a, b), in place:
@@ -1118,10 +1120,13 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
         }
     }
     __syncthreads();
-    // apply kernels: the first faces' per-point data in flight during the line phases
+    // apply kernels: the first faces' per-point data in flight during the line
+    // phases (orders whose own traces come from registers: after the pointwise
+    // terms, which keeps them within the register budget of 3 waves per SIMD)
     FaceU<R> fu0, fu1;
     FaceD<R> fd0, fd1;
-    if constexpr (MODE != 3) {
+    constexpr bool FACE_LATE = MODE == 1 && S::OWN;
+    if constexpr (MODE != 3 && !FACE_LATE) {
         fu0 = face_uniform<R>(meta, 0);
         fd0 = load_face<R, P, MODE>(D, fu0, 0);
         fu1 = face_uniform<R>(meta, 1);
@@ -1194,13 +1199,11 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
         z_db[0] = SB[pa<P>(a, b, 0)];
         z_db[1] = SB[pa<P>(a, b, N - 1)];
     }
-    R *OS = SA + 2 * S::ARR;   // own-field stash (S::OWN)
+    R *OS = SA + S::STASH_OFF;   // own-field stash (S::OWN), over the point arrays
     if constexpr (MODE == 1 && S::OWN) {
-        // own (u, g) of the faces normal to xi_0 now; the others' fields kept
-        fd0.ou = x_u[0];
-        fd0.og = fd0.Ck * x_dk[0] + fd0.Ca * x_da[0] + fd0.Cb * x_db[0];
-        fd1.ou = x_u[1];
-        fd1.og = fd1.Ck * x_dk[1] + fd1.Ca * x_da[1] + fd1.Cb * x_db[1];
+        __syncthreads();   // every lane's point-array reads before the stash overwrites them
+        // the fields of the faces normal to xi_1 and xi_2 kept in the stash;
+        // those normal to xi_0 stay in registers
         if (col) {
             const R st[16] = {y_u[0], y_dk[0], y_da[0], y_db[0], y_u[1], y_dk[1], y_da[1], y_db[1],
                               z_u[0], z_dk[0], z_da[0], z_db[0], z_u[1], z_dk[1], z_da[1], z_db[1]};
@@ -1217,6 +1220,17 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     // pointwise: m = lambda w|J| u, q = (G w) grad_xi u  (in place: u <- m, d <- q);
     // in chunks, so that the factor loads of one chunk are in flight together
     if (col) pointwise<R, P, GEO>(D, ed, a, b, u, d0, d1, d2);
+        if constexpr (FACE_LATE) {
+            fu0 = face_uniform<R>(meta, 0);
+            fd0 = load_face<R, P, MODE>(D, fu0, 0);
+            fu1 = face_uniform<R>(meta, 1);
+            fd1 = load_face<R, P, MODE>(D, fu1, 0);
+            // own (u, g) of the faces normal to xi_0 from the registers
+            fd0.ou = x_u[0];
+            fd0.og = fd0.Ck * x_dk[0] + fd0.Ca * x_da[0] + fd0.Cb * x_db[0];
+            fd1.ou = x_u[1];
+            fd1.og = fd1.Ck * x_dk[1] + fd1.Ca * x_da[1] + fd1.Cb * x_db[1];
+        }
 
         // faces, both of one direction at a time: flux from the trace buffer,
         // lifted back to the face points, added to the pointwise terms.
@@ -1362,6 +1376,7 @@ __device__ __forceinline__ void k3g_elem(const Args &A, const Data<R> &D, int bl
     }
 
     // IProduct: y = B^T (m + D_0^T q_0 + D_1^T q_1 + D_2^T q_2)
+    if constexpr (MODE == 1 && S::OWN) __syncthreads();   // the stash reads before the point arrays return
     R z[N];
     if (col) {
 #pragma unroll
@@ -1786,10 +1801,13 @@ __host__ __device__ constexpr int lds_mode(int mode) {
 // Waves per SIMD the compiler sizes the registers of a kernel for.  The FP64
 // map-geometry applies of orders 3 and 4 fit 3 waves (168 VGPRs; order 4 with
 // a 60-byte spill) and gain 7 and 3 us on the 32^3 mesh; orders 5 and 6 spill
-// 132 and 204 bytes there and lose, so they stay at 2.
+// 132 and 204 bytes there and lose, so they stay at 2.  The FP64 stored-factor
+// apply of order 6 fits 3 waves (16-byte spill; its stash shares the face
+// scratch, so its LDS allows 3 as well) and gains 5 us.
 template <class R, int P, int MODE, int GEO = GEO_POINT>
 struct Occ {
-    static constexpr int V = (GEO == GEO_MAP && sizeof(R) == 8 && (P == 3 || P == 4)) ? 3 : 2;
+    static constexpr int V = (GEO == GEO_MAP && sizeof(R) == 8 && (P == 3 || P == 4)) ? 3
+                             : (sizeof(R) == 8 && P == 6 && MODE == 1 && GEO == GEO_POINT) ? 3 : 2;
 };
 
 // One launch per order group (and per affine / deformed part of it): block b
