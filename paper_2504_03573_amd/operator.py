@@ -15,13 +15,21 @@ import torch
 from . import _capi as C
 
 
-def _stream_ptr(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+def _stream_ptr(stream=None, device_index=None):
+    """The HIP stream handle to launch on: ``stream``'s, else the current
+    stream of ``device_index`` (the current device if None)."""
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    if device_index is None:
+        device_index = torch.cuda.current_device()
+    return ctypes.c_void_p(torch._C._cuda_getCurrentRawStream(device_index))
 
 
 def _ptr(t: torch.Tensor):
     return ctypes.c_void_p(t.data_ptr())
+
+
+_PREC = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}
 
 
 class _Desc:
@@ -95,6 +103,7 @@ class SipdgOperator:
         C.check(self._lib.sipdg_num_affine(self._h, ctypes.byref(n)))
         self.n_affine = n.value   # elements whose apply uses per-element geometry
         self.device = torch.device("cuda", torch.cuda.current_device())
+        self._dev = self.device.index
 
     @classmethod
     def batch(cls, meshes, basis: str = "legendre"):
@@ -119,7 +128,7 @@ class SipdgOperator:
     # ------------------------------------------------------------------ checks
     def _vec(self, t, dtype, n=None, name="vector"):
         n = self.n_dofs if n is None else n
-        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
             raise TypeError(f"{name} must be a device tensor")
         if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
             raise ValueError(f"{name}: need contiguous {dtype} with {n} entries, got {t.dtype} {tuple(t.shape)}")
@@ -127,44 +136,44 @@ class SipdgOperator:
 
     # ------------------------------------------------------------------ operator
     def apply(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        prec = _PREC.get(x.dtype)
         if prec is None:
             raise TypeError("x must be float64 or float32")
         self._vec(x, x.dtype, name="x")
         y = torch.empty_like(x) if out is None else self._vec(out, x.dtype, name="out")
-        C.check(self._lib.sipdg_apply(self._h, _ptr(x), _ptr(y), prec, _stream_ptr(stream)))
+        C.check(self._lib.sipdg_apply(self._h, x.data_ptr(), y.data_ptr(), prec, _stream_ptr(stream, self._dev)))
         return y
 
     def apply_noalloc(self, x: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
         """y = A x through sipdg_apply_noalloc: the trace buffer is the
         library's fixed per-GPU scratch array, so the call allocates nothing
         (``out`` must be given).  Calls on one GPU must not overlap."""
-        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        prec = _PREC.get(x.dtype)
         if prec is None:
             raise TypeError("x must be float64 or float32")
         self._vec(x, x.dtype, name="x")
         self._vec(out, x.dtype, name="out")
-        C.check(self._lib.sipdg_apply_noalloc(self._h, _ptr(x), _ptr(out), prec, _stream_ptr(stream)))
+        C.check(self._lib.sipdg_apply_noalloc(self._h, _ptr(x), _ptr(out), prec, _stream_ptr(stream, self._dev)))
         return out
 
     def apply_stage(self, x: torch.Tensor, stage: int, out: torch.Tensor | None = None, stream=None):
         """Stage 1 (trace values into the handle's buffer) or stage 2 (fluxes,
         volume terms, inner products into ``out``) of one application."""
-        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        prec = _PREC.get(x.dtype)
         if prec is None:
             raise TypeError("x must be float64 or float32")
         self._vec(x, x.dtype, name="x")
         if stage == 2:
             out = torch.empty_like(x) if out is None else self._vec(out, x.dtype, name="out")
         C.check(self._lib.sipdg_apply_stage(self._h, _ptr(x), _ptr(out) if out is not None else None,
-                                            prec, int(stage), _stream_ptr(stream)))
+                                            prec, int(stage), _stream_ptr(stream, self._dev)))
         return out
 
     def apply_timed(self, x: torch.Tensor, out: torch.Tensor, reps: int = 20, stream=None) -> list[dict]:
         """Run ``reps`` applications with a HIP event around every kernel
         launch; per launch of one application: mean ms, stage, order, element
         count and the algorithmic bytes of its elements (apply launches)."""
-        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(x.dtype)
+        prec = _PREC.get(x.dtype)
         if prec is None:
             raise TypeError("x must be float64 or float32")
         self._vec(x, x.dtype, name="x")
@@ -172,17 +181,17 @@ class SipdgOperator:
         info = (C.LaunchInfo * 64)()
         n = ctypes.c_int()
         C.check(self._lib.sipdg_apply_timed(self._h, _ptr(x), _ptr(out), prec, int(reps), info, 64,
-                                            ctypes.byref(n), _stream_ptr(stream)))
+                                            ctypes.byref(n), _stream_ptr(stream, self._dev)))
         return [{"ms": info[i].ms, "stage": info[i].stage, "order": info[i].order,
                  "elements": int(info[i].elements), "alg_bytes": info[i].alg_bytes} for i in range(n.value)]
 
     def apply_transpose(self, g: torch.Tensor, out: torch.Tensor | None = None, stream=None):
-        prec = {torch.float64: C.SIPDG_F64, torch.float32: C.SIPDG_F32}.get(g.dtype)
+        prec = _PREC.get(g.dtype)
         if prec is None:
             raise TypeError("g must be float64 or float32")
         self._vec(g, g.dtype, name="g")
         y = torch.empty_like(g) if out is None else self._vec(out, g.dtype, name="out")
-        C.check(self._lib.sipdg_apply_transpose(self._h, _ptr(g), _ptr(y), prec, _stream_ptr(stream)))
+        C.check(self._lib.sipdg_apply_transpose(self._h, _ptr(g), _ptr(y), prec, _stream_ptr(stream, self._dev)))
         return y
 
     @property
@@ -253,7 +262,7 @@ class SipdgOperator:
         a JSON file of earlier results is consulted first and updated."""
         ms = (ctypes.c_double * len(C.VARIANTS))()
         cp = None if cache_path is None else str(cache_path).encode()
-        C.check(self._lib.sipdg_autotune(self._h, cp, int(reps), ms, _stream_ptr(stream)))
+        C.check(self._lib.sipdg_autotune(self._h, cp, int(reps), ms, _stream_ptr(stream, self._dev)))
         return {name: ms[i] for name, i in C.VARIANTS.items() if ms[i] > 0}
 
     def set_tile(self, order: int, tile: int, budget: int):
@@ -270,7 +279,7 @@ class SipdgOperator:
 
     def diagonal(self, stream=None) -> torch.Tensor:
         d = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
-        C.check(self._lib.sipdg_diagonal(self._h, _ptr(d), _stream_ptr(stream)))
+        C.check(self._lib.sipdg_diagonal(self._h, _ptr(d), _stream_ptr(stream, self._dev)))
         return d
 
     def param_grad(self, a: torch.Tensor, b: torch.Tensor, stream=None):
@@ -279,7 +288,7 @@ class SipdgOperator:
         dl = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
         ds = torch.empty(self.n_problems, dtype=torch.float64, device=self.device)
         C.check(self._lib.sipdg_param_grad(self._h, _ptr(a), _ptr(b), _ptr(dl), _ptr(ds),
-                                           _stream_ptr(stream)))
+                                           _stream_ptr(stream, self._dev)))
         return dl, ds
 
     # Every change of lambda or sigma bumps ``param_generation``, so a cache of
@@ -290,7 +299,7 @@ class SipdgOperator:
     def set_lambda(self, lam: torch.Tensor, stream=None):
         self._vec(lam, torch.float64, n=self.n_elems, name="lambda")
         self.param_generation += 1
-        C.check(self._lib.sipdg_set_lambda(self._h, _ptr(lam), _stream_ptr(stream)))
+        C.check(self._lib.sipdg_set_lambda(self._h, _ptr(lam), _stream_ptr(stream, self._dev)))
 
     def set_penalty_scale(self, sigma: float, problem: int = -1):
         self.param_generation += 1
@@ -299,7 +308,7 @@ class SipdgOperator:
     def quad_points(self, stream=None):
         xq = torch.empty((self.n_volume_points, self.dim), dtype=torch.float64, device=self.device)
         xb = torch.empty((max(self.n_boundary_points, 1), self.dim), dtype=torch.float64, device=self.device)
-        C.check(self._lib.sipdg_quad_points(self._h, _ptr(xq), _ptr(xb), _stream_ptr(stream)))
+        C.check(self._lib.sipdg_quad_points(self._h, _ptr(xq), _ptr(xb), _stream_ptr(stream, self._dev)))
         return xq, xb[: self.n_boundary_points]
 
     def load_vector(self, s: torch.Tensor, g: torch.Tensor, stream=None) -> torch.Tensor:
@@ -308,7 +317,7 @@ class SipdgOperator:
             self._vec(g, torch.float64, n=self.n_boundary_points, name="g")
         b = torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
         C.check(self._lib.sipdg_load_vector(self._h, _ptr(s), _ptr(g) if self.n_boundary_points else None,
-                                            _ptr(b), _stream_ptr(stream)))
+                                            _ptr(b), _stream_ptr(stream, self._dev)))
         return b
 
     def rhs(self, source, dirichlet) -> torch.Tensor:
@@ -329,7 +338,7 @@ class SipdgOperator:
         o.tol, o.restart, o.maxit, o.precond = float(tol), int(restart), int(maxit), int(bool(precond))
         info = C.GmresInfo()
         rc = self._lib.sipdg_gmres_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
-                                         _stream_ptr(stream))
+                                         _stream_ptr(stream, self._dev))
         out = {"iters": info.iters, "restarts": info.restarts, "converged": bool(info.converged),
                "rel_resid": info.rel_resid, "time_ms": info.time_ms}
         if rc != 0 and not (rc == -5 and not raise_on_fail):
@@ -370,7 +379,7 @@ class SipdgOperator:
             o.x0_given = 1
         info = C.CgInfo()
         rc = self._lib.sipdg_cg_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(o), ctypes.byref(info),
-                                      _stream_ptr(stream))
+                                      _stream_ptr(stream, self._dev))
         out = {"iters": info.iters, "outer_iters": info.outer_iters, "converged": bool(info.converged),
                "rel_resid": info.rel_resid, "time_ms": info.time_ms, "status": rc}
         if raise_on_fail:
