@@ -33,7 +33,7 @@ struct CgWork {
     CgScalars S{};
     double *d_sc = nullptr;   // backing store of the double scalars
     int *d_si = nullptr;      // backing store of the int scalars
-    double *p1 = nullptr, *p2 = nullptr;
+    double *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;   // reduction partials (p3: p.q)
     double *x64 = nullptr, *r64 = nullptr, *z64 = nullptr, *pp64 = nullptr, *q64 = nullptr;
     float *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *pp32 = nullptr, *q32 = nullptr;
     double *d_norm = nullptr, *d_bnorm = nullptr;
@@ -51,7 +51,7 @@ void free_cg(sipdg_ctx *c) {
     if (w->g64) (void)hipGraphExecDestroy(w->g64);
     if (w->g32) (void)hipGraphExecDestroy(w->g32);
     void *ptrs[] = {w->d_blk_start, w->d_blk_prob, w->d_prob_blk, w->d_done, w->d_sc, w->d_si,
-                    w->p1, w->p2, w->x64, w->r64, w->z64, w->pp64, w->q64, w->x32, w->r32,
+                    w->p1, w->p2, w->p3, w->x64, w->r64, w->z64, w->pp64, w->q64, w->x32, w->r32,
                     w->z32, w->pp32, w->q32, w->d_norm, w->d_bnorm, w->d_preconv, w->d_ratio};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -118,6 +118,7 @@ static int ensure_cg(sipdg_ctx *c) {
     w->S.nfin = w->d_si + 2 * np + 3;
     ALLOC(w->p1, nblk);
     ALLOC(w->p2, nblk);
+    ALLOC(w->p3, nblk);
     const int64_t n = c->ndof;
     ALLOC(w->x64, n);
     ALLOC(w->r64, n);
@@ -163,10 +164,10 @@ static bool use_fold(const sipdg_ctx *c) {
 }
 
 // One CG iteration in precision R on the work vectors.
-//   separate: q = A p; p.q; alpha; x += alpha p, r -= alpha q, z = M r (with
-//             r.r, r.z); beta; p = z + beta p.
+//   separate: q = A p; p.q; [alpha, formed by every block of] x += alpha p,
+//             r -= alpha q, z = M r (with r.r, r.z); beta; p = z + beta p.
 //   folded:   [x += alpha p, p = M r + beta p, in the trace stage] q = A p;
-//             p.q; alpha; r -= alpha q (with r.r, r.z); beta.  Same values
+//             p.q; [alpha] r -= alpha q (with r.r, r.z); beta.  Same values
 //             bit for bit; the last x update is applied by vec_flush.
 template <class R>
 static int cg_body(sipdg_ctx *c, bool precond, bool fold) {
@@ -185,17 +186,15 @@ static int cg_body(sipdg_ctx *c, bool precond, bool fold) {
         const CgFold<R> f{p, x, r, dinv, w->S.alpha, w->S.beta, w->S.conv};
         int rc = apply_impl<R>(c, p, q, (R *)c->d_tbuf, w->d_done, st, 3, nullptr, &f);
         if (rc) return rc;
-        HIPCHK(vec_dot<R>(w->V, p, q, w->p1, st));
-        HIPCHK(vec_fin_alpha(w->V, w->S, w->p1, st));
-        HIPCHK(vec_update_fold<R>(w->V, w->S, r, q, dinv, w->p1, w->p2, st));
+        HIPCHK(vec_dot<R>(w->V, p, q, w->p3, st));
+        HIPCHK(vec_update_fold<R>(w->V, w->S, r, q, dinv, w->p3, w->p1, w->p2, st));
         HIPCHK(vec_fin_beta(w->V, w->S, w->p1, w->p2, st));
         return SIPDG_OK;
     }
     int rc = apply_impl<R>(c, p, q, (R *)c->d_tbuf, w->d_done, st);
     if (rc) return rc;
-    HIPCHK(vec_dot<R>(w->V, p, q, w->p1, st));
-    HIPCHK(vec_fin_alpha(w->V, w->S, w->p1, st));
-    HIPCHK(vec_update<R>(w->V, w->S, x, r, p, q, dinv, z, w->p1, w->p2, st));
+    HIPCHK(vec_dot<R>(w->V, p, q, w->p3, st));
+    HIPCHK(vec_update<R>(w->V, w->S, x, r, p, q, dinv, z, w->p3, w->p1, w->p2, st));
     HIPCHK(vec_fin_beta(w->V, w->S, w->p1, w->p2, st));
     HIPCHK(vec_pupdate<R>(w->V, w->S, z, p, st));
     return SIPDG_OK;

@@ -33,16 +33,21 @@ struct CgScalars {
 
 template <class R>
 hipError_t vec_dot(const VecCtx &V, const R *a, const R *b, double *partial, hipStream_t st);
+// alpha of each problem from the p.q partials ppq (every block forms the same
+// fixed-order sum; the problem's first block records it), then x += alpha p,
+// r -= alpha q, z = M r with the partials of r.r and r.z.  ppq must not alias
+// prr or prz (blocks read ppq while others write their r.r partials).
 template <class R>
 hipError_t vec_update(const VecCtx &V, const CgScalars &S, R *x, R *r, const R *p, const R *q,
-                      const R *dinv, R *z, double *prr, double *prz, hipStream_t st);
+                      const R *dinv, R *z, const double *ppq, double *prr, double *prz, hipStream_t st);
 template <class R>
 hipError_t vec_pupdate(const VecCtx &V, const CgScalars &S, const R *z, R *p, hipStream_t st);
 // folded CG step (x and p updated in the next application's trace stage):
-// r -= alpha q with the partials of r.r and r.z, and the deferred x update
+// alpha as in vec_update, r -= alpha q with the partials of r.r and r.z, and
+// the deferred x update
 template <class R>
-hipError_t vec_update_fold(const VecCtx &V, const CgScalars &S, R *r, const R *q, const R *dinv, double *prr,
-                           double *prz, hipStream_t st);
+hipError_t vec_update_fold(const VecCtx &V, const CgScalars &S, R *r, const R *q, const R *dinv,
+                           const double *ppq, double *prr, double *prz, hipStream_t st);
 template <class R>
 hipError_t vec_flush(const VecCtx &V, const CgScalars &S, R *x, const R *p, hipStream_t st);
 template <class R>
@@ -50,7 +55,6 @@ hipError_t vec_start(const VecCtx &V, const R *r, const R *dinv, R *z, R *p, R *
                      double *prz, hipStream_t st);
 template <class R>
 hipError_t vec_fill(R *v, int64_t n, R val, hipStream_t st);
-hipError_t vec_fin_alpha(const VecCtx &V, const CgScalars &S, const double *ppq, hipStream_t st);
 hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,
                         hipStream_t st);
 hipError_t vec_fin_start(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz,

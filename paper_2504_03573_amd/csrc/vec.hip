@@ -32,62 +32,6 @@ __global__ __launch_bounds__(VB) void k_dot(VecCtx V, const R *a, const R *b, do
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-// x += alpha p, r -= alpha q, z = dinv r; partials of r.r and r.z
-template <class R>
-__global__ __launch_bounds__(VB) void k_update(VecCtx V, const CgScalars S, R *x, R *r, const R *p,
-                                               const R *q, const R *dinv, R *z, double *prr,
-                                               double *prz) {
-    if (V.done && *V.done) return;
-    __shared__ double red[VB];
-    const int prob = V.blk_prob[blockIdx.x];
-    const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
-    const double alpha = S.alpha[prob];
-    double rr = 0.0, rz = 0.0;
-    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
-        const R xi = (R)((double)x[i] + alpha * (double)p[i]);
-        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
-        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
-        x[i] = xi;
-        r[i] = ri;
-        z[i] = zi;
-        rr += (double)ri * (double)ri;
-        rz += (double)ri * (double)zi;
-    }
-    rr = block_sum(rr, red);
-    rz = block_sum(rz, red);
-    if (threadIdx.x == 0) {
-        prr[blockIdx.x] = rr;
-        prz[blockIdx.x] = rz;
-    }
-}
-
-// r -= alpha q; partials of r.r and r.z with z = dinv r (not stored): the
-// update of the folded CG step, whose x and p updates happen in the next
-// application's trace stage (or in k_flush)
-template <class R>
-__global__ __launch_bounds__(VB) void k_update_fold(VecCtx V, const CgScalars S, R *r, const R *q, const R *dinv,
-                                                    double *prr, double *prz) {
-    if (V.done && *V.done) return;
-    __shared__ double red[VB];
-    const int prob = V.blk_prob[blockIdx.x];
-    const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
-    const double alpha = S.alpha[prob];
-    double rr = 0.0, rz = 0.0;
-    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
-        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
-        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
-        r[i] = ri;
-        rr += (double)ri * (double)ri;
-        rz += (double)ri * (double)zi;
-    }
-    rr = block_sum(rr, red);
-    rz = block_sum(rz, red);
-    if (threadIdx.x == 0) {
-        prr[blockIdx.x] = rr;
-        prz[blockIdx.x] = rz;
-    }
-}
-
 // The deferred x update of the folded CG step: x += alpha p (every block;
 // never skipped), then alpha = 0 (k_alpha_zero) so that it is applied once.
 template <class R>
@@ -170,22 +114,81 @@ __device__ inline bool last_vote(int *nact, int *nfin, bool active, int &total) 
     return true;
 }
 
-// alpha = rho / p.q per problem (0 once converged); breakdown if p.q <= 0.
-// One block per problem.
-__global__ __launch_bounds__(VB) void k_fin_alpha(VecCtx V, CgScalars S, const double *ppq) {
+// alpha = rho / p.q of problem p (0 once converged, and on a breakdown,
+// p.q <= 0), from the problem's p.q partials: every block of the problem
+// forms the same fixed-order sum, so every block has the same alpha without a
+// separate launch; the problem's first block records alpha (for the next trace
+// stage and k_flush) and a breakdown.  A breakdown gives alpha = 0 whether or
+// not a block already sees the breakdown mark.
+__device__ inline double block_alpha(const VecCtx &V, const CgScalars &S, const double *ppq, int p, double *red) {
+    const double pq = seg_sum(ppq, V.prob_blk[p], V.prob_blk[p + 1], red);
+    const int c = S.conv[p];
+    const double alpha = (c || !(pq > 0.0)) ? 0.0 : S.rho[p] / pq;
+    if (threadIdx.x == 0 && (int)blockIdx.x == V.prob_blk[p]) {
+        S.alpha[p] = alpha;
+        if (!c && !(pq > 0.0)) {
+            S.conv[p] = 2;   // breakdown
+            atomicOr(S.flags, 2);
+        }
+    }
+    return alpha;
+}
+
+// alpha from the p.q partials (block_alpha); x += alpha p, r -= alpha q,
+// z = dinv r; partials of r.r and r.z
+template <class R>
+__global__ __launch_bounds__(VB) void k_update(VecCtx V, const CgScalars S, R *x, R *r, const R *p,
+                                               const R *q, const R *dinv, R *z, const double *ppq,
+                                               double *prr, double *prz) {
     if (V.done && *V.done) return;
     __shared__ double red[VB];
-    const int p = blockIdx.x;
-    const double pq = seg_sum(ppq, V.prob_blk[p], V.prob_blk[p + 1], red);
-    if (threadIdx.x != 0) return;
-    if (S.conv[p]) {
-        S.alpha[p] = 0.0;
-    } else if (!(pq > 0.0)) {
-        S.alpha[p] = 0.0;
-        S.conv[p] = 2;   // breakdown
-        atomicOr(S.flags, 2);
-    } else {
-        S.alpha[p] = S.rho[p] / pq;
+    const int prob = V.blk_prob[blockIdx.x];
+    const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
+    const double alpha = block_alpha(V, S, ppq, prob, red);
+    double rr = 0.0, rz = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
+        const R xi = (R)((double)x[i] + alpha * (double)p[i]);
+        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
+        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
+        x[i] = xi;
+        r[i] = ri;
+        z[i] = zi;
+        rr += (double)ri * (double)ri;
+        rz += (double)ri * (double)zi;
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = rr;
+        prz[blockIdx.x] = rz;
+    }
+}
+
+// alpha from the p.q partials (block_alpha); r -= alpha q; partials of r.r
+// and r.z with z = dinv r (not stored): the update of the folded CG step,
+// whose x and p updates happen in the next application's trace stage (or in
+// k_flush)
+template <class R>
+__global__ __launch_bounds__(VB) void k_update_fold(VecCtx V, const CgScalars S, R *r, const R *q, const R *dinv,
+                                                    const double *ppq, double *prr, double *prz) {
+    if (V.done && *V.done) return;
+    __shared__ double red[VB];
+    const int prob = V.blk_prob[blockIdx.x];
+    const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
+    const double alpha = block_alpha(V, S, ppq, prob, red);
+    double rr = 0.0, rz = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
+        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
+        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
+        r[i] = ri;
+        rr += (double)ri * (double)ri;
+        rz += (double)ri * (double)zi;
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = rr;
+        prz[blockIdx.x] = rz;
     }
 }
 
@@ -362,16 +365,16 @@ hipError_t vec_dot(const VecCtx &V, const R *a, const R *b, double *partial, hip
 }
 template <class R>
 hipError_t vec_update(const VecCtx &V, const CgScalars &S, R *x, R *r, const R *p, const R *q,
-                      const R *dinv, R *z, double *prr, double *prz, hipStream_t st) {
+                      const R *dinv, R *z, const double *ppq, double *prr, double *prz, hipStream_t st) {
     if (V.nblk == 0) return hipSuccess;   // no DOFs
-    hipLaunchKernelGGL(k_update<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, x, r, p, q, dinv, z, prr, prz);
+    hipLaunchKernelGGL(k_update<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, x, r, p, q, dinv, z, ppq, prr, prz);
     LCHK();
 }
 template <class R>
-hipError_t vec_update_fold(const VecCtx &V, const CgScalars &S, R *r, const R *q, const R *dinv, double *prr,
-                           double *prz, hipStream_t st) {
+hipError_t vec_update_fold(const VecCtx &V, const CgScalars &S, R *r, const R *q, const R *dinv,
+                           const double *ppq, double *prr, double *prz, hipStream_t st) {
     if (V.nblk == 0) return hipSuccess;   // no DOFs
-    hipLaunchKernelGGL(k_update_fold<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, r, q, dinv, prr, prz);
+    hipLaunchKernelGGL(k_update_fold<R>, dim3(V.nblk), dim3(VB), 0, st, V, S, r, q, dinv, ppq, prr, prz);
     LCHK();
 }
 template <class R>
@@ -401,10 +404,6 @@ hipError_t vec_fill(R *v, int64_t n, R val, hipStream_t st) {
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_fill<R>, dim3(g), dim3(256), 0, st, v, n, val);
-    LCHK();
-}
-hipError_t vec_fin_alpha(const VecCtx &V, const CgScalars &S, const double *ppq, hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_alpha, dim3(V.nprob), dim3(VB), 0, st, V, S, ppq);
     LCHK();
 }
 hipError_t vec_fin_beta(const VecCtx &V, const CgScalars &S, const double *prr, const double *prz, hipStream_t st) {
@@ -445,10 +444,11 @@ hipError_t vec_correct(const VecCtx &V, const float *d32, const double *nrm, dou
 #define INST(R)                                                                                       \
     template hipError_t vec_dot<R>(const VecCtx &, const R *, const R *, double *, hipStream_t);     \
     template hipError_t vec_update<R>(const VecCtx &, const CgScalars &, R *, R *, const R *,         \
-                                      const R *, const R *, R *, double *, double *, hipStream_t);    \
+                                      const R *, const R *, R *, const double *, double *, double *,  \
+                                      hipStream_t);                                                   \
     template hipError_t vec_pupdate<R>(const VecCtx &, const CgScalars &, const R *, R *, hipStream_t); \
-    template hipError_t vec_update_fold<R>(const VecCtx &, const CgScalars &, R *, const R *, const R *, double *, \
-                                           double *, hipStream_t);                                              \
+    template hipError_t vec_update_fold<R>(const VecCtx &, const CgScalars &, R *, const R *, const R *,        \
+                                           const double *, double *, double *, hipStream_t);                    \
     template hipError_t vec_flush<R>(const VecCtx &, const CgScalars &, R *, const R *, hipStream_t);            \
     template hipError_t vec_start<R>(const VecCtx &, const R *, const R *, R *, R *, R *, double *,   \
                                      double *, hipStream_t);                                          \
