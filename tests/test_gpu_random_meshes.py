@@ -94,3 +94,30 @@ def test_random_mesh_parity(P, orc, seed):
     yb = bop.apply(torch.cat([xt, xt])).cpu().numpy()
     n = op.n_dofs
     assert rel(yb[:n], y_ref) <= 1e-12 and rel(yb[n:], y_ref) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_random_mesh_diagonal_gradients_p2p(P, orc, seed):
+    """On the same meshes: the Jacobi diagonal, the transpose application
+    (the operator is symmetric), the lambda and penalty-scale gradients of
+    a^T A b, and the point-to-point flux (3-D meshes)."""
+    mesh = _mesh(seed)
+    print(f"[random mesh {seed}: diagonal, transpose, gradients, p2p]", flush=True)
+    op = P.SipdgOperator(mesh)
+    om = orc.prepare(mesh)
+    assert rel(op.diagonal().cpu().numpy(), om.diagonal()) <= 1e-12
+    a = synth.random_coefficients(mesh, 9400 + seed)
+    b = synth.random_coefficients(mesh, 9500 + seed)
+    at, bt = torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")
+    y = op.apply(at).cpu().numpy()
+    assert rel(op.apply_transpose(at).cpu().numpy(), y) <= 1e-13
+    dl, ds = op.param_grad(at, bt)
+    dl_ref, ds_ref = om.param_grad(a, b)
+    assert rel(dl.cpu().numpy(), dl_ref) <= 1e-12
+    assert abs(float(ds.sum()) - ds_ref) <= 1e-12 * max(abs(ds_ref), 1.0)
+    try:
+        op.flux = "p2p"
+    except P.SipdgError:
+        assert mesh.dim == 2   # the point-to-point flux is built for 3-D meshes
+        return
+    assert rel(op.apply(at).cpu().numpy(), om.apply_p2p(a)) <= 1e-12
