@@ -121,3 +121,27 @@ def test_random_mesh_diagonal_gradients_p2p(P, orc, seed):
         assert mesh.dim == 2   # the point-to-point flux is built for 3-D meshes
         return
     assert rel(op.apply(at).cpu().numpy(), om.apply_p2p(a)) <= 1e-12
+
+
+@pytest.mark.parametrize("seed", list(range(12)))
+def test_random_batch_solves(P, orc, seed):
+    """Batches of two to four random meshes of one dimension solved to 1e-10
+    in FP64 and in FP32 inside FP64 refinement: every problem's residual,
+    recomputed with the oracle's operator, meets the tolerance."""
+    rng = np.random.default_rng(9600 + seed)
+    # one dimension per batch (3-D for most seeds, 2-D for every fourth)
+    pool = [s for s in SEEDS if (s % 4 == 0) == (seed % 4 == 0)]
+    meshes = [_mesh(int(s)) for s in rng.choice(pool, size=int(rng.integers(2, 5)), replace=False)]
+    print(f"[random batch {seed}: {len(meshes)} problems]", flush=True)
+    bop = P.SipdgOperator.batch(meshes)
+    off = bop.problem_dof_offsets
+    b = rng.standard_normal(bop.n_dofs)
+    bt = torch.tensor(b, device="cuda")
+    for mode in ("f64", "f32_ir"):
+        xs, info = bop.cg_solve(bt, tol=1e-10, mode=mode)
+        assert info["converged"], (mode, info)
+        x = xs.cpu().numpy()
+        for i, m in enumerate(meshes):
+            s = slice(int(off[i]), int(off[i + 1]))
+            r = b[s] - orc.prepare(m).apply(x[s])
+            assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b[s]), (mode, i)
