@@ -73,6 +73,9 @@ def test_random_mesh_parity(P, orc, seed):
         e32 = rel(op.apply(xt.float()).double().cpu().numpy(), y_ref)
         assert e32 <= 1e-5, (v, e32)
     op.variant = "gather_fold"
+    # the allocation-free entry point gives the same bits
+    y = op.apply(xt)
+    assert torch.equal(op.apply_noalloc(xt, torch.empty_like(xt)), y)
     # the modified C0 modal basis on the default structure
     op.basis = "modal"
     e = rel(op.apply(xt).cpu().numpy(), orc.prepare(mesh, basis="modal").apply(x))
