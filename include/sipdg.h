@@ -342,7 +342,10 @@ int sipdg_get_geometry(sipdg_handle h, int *source);
  * every allowed kernel structure, the persistent structure's grid (blocks
  * per compute unit), and for the gather-fold structure the tile shape of
  * each order group (elements per workgroup and the register budget, see
- * sipdg_tuning), and keeps the fastest.
+ * sipdg_tuning), and keeps the fastest.  A tile shape is timed in
+ * alternation with the order group's best shape so far (twice each, the
+ * faster run of each kept) and replaces it only if it is more than 2 %
+ * faster.
  * cache_path (host string, may be NULL): a JSON file of earlier results, one
  * record per key "<mesh signature>-<library source hash>-<GPU arch>-<CUs>".
  * A record with this handle's key is applied without timing; otherwise the
