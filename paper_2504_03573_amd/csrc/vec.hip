@@ -7,6 +7,7 @@
 namespace sipdg {
 
 constexpr int VB = 256;   // threads per vector block
+constexpr int UB = 8;     // entries per thread whose loads are issued together
 
 __device__ inline double block_sum(double v, double *red) {
     red[threadIdx.x] = v;
@@ -27,7 +28,19 @@ __global__ __launch_bounds__(VB) void k_dot(VecCtx V, const R *a, const R *b, do
     __shared__ double red[VB];
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
     double acc = 0.0;
-    for (int64_t i = s + threadIdx.x; i < e; i += VB) acc += (double)a[i] * (double)b[i];
+    // UB entries per thread loaded before they are added (in the same order)
+    for (int64_t i0 = s + threadIdx.x; i0 < e; i0 += UB * VB) {
+        R av[UB], bv[UB];
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int64_t i = i0 + j * VB;
+            av[j] = i < e ? a[i] : R(0);
+            bv[j] = i < e ? b[i] : R(0);
+        }
+#pragma unroll
+        for (int j = 0; j < UB; ++j)
+            if (i0 + j * VB < e) acc += (double)av[j] * (double)bv[j];
+    }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
@@ -146,15 +159,32 @@ __global__ __launch_bounds__(VB) void k_update(VecCtx V, const CgScalars S, R *x
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
     const double alpha = block_alpha(V, S, ppq, prob, red);
     double rr = 0.0, rz = 0.0;
-    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
-        const R xi = (R)((double)x[i] + alpha * (double)p[i]);
-        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
-        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
-        x[i] = xi;
-        r[i] = ri;
-        z[i] = zi;
-        rr += (double)ri * (double)ri;
-        rz += (double)ri * (double)zi;
+    for (int64_t i0 = s + threadIdx.x; i0 < e; i0 += UB * VB) {
+        R xv[UB], pv[UB], rv[UB], qv[UB], dv[UB];
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int64_t i = i0 + j * VB;
+            const bool in = i < e;
+            xv[j] = in ? x[i] : R(0);
+            pv[j] = in ? p[i] : R(0);
+            rv[j] = in ? r[i] : R(0);
+            qv[j] = in ? q[i] : R(0);
+            dv[j] = in && dinv ? dinv[i] : R(1);
+        }
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int64_t i = i0 + j * VB;
+            if (i < e) {
+                const R xi = (R)((double)xv[j] + alpha * (double)pv[j]);
+                const R ri = (R)((double)rv[j] - alpha * (double)qv[j]);
+                const R zi = dinv ? (R)((double)dv[j] * (double)ri) : ri;
+                x[i] = xi;
+                r[i] = ri;
+                z[i] = zi;
+                rr += (double)ri * (double)ri;
+                rz += (double)ri * (double)zi;
+            }
+        }
     }
     rr = block_sum(rr, red);
     rz = block_sum(rz, red);
@@ -175,14 +205,40 @@ __global__ __launch_bounds__(VB) void k_update_fold(VecCtx V, const CgScalars S,
     __shared__ double red[VB];
     const int prob = V.blk_prob[blockIdx.x];
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
+    // the first UB entries per thread are requested before alpha is formed
+    int64_t i0 = s + threadIdx.x;
+    R rv[UB], qv[UB], dv[UB];
+#pragma unroll
+    for (int j = 0; j < UB; ++j) {
+        const int64_t i = i0 + j * VB;
+        const bool in = i < e;
+        rv[j] = in ? r[i] : R(0);
+        qv[j] = in ? q[i] : R(0);
+        dv[j] = in && dinv ? dinv[i] : R(1);
+    }
     const double alpha = block_alpha(V, S, ppq, prob, red);
     double rr = 0.0, rz = 0.0;
-    for (int64_t i = s + threadIdx.x; i < e; i += VB) {
-        const R ri = (R)((double)r[i] - alpha * (double)q[i]);
-        const R zi = dinv ? (R)((double)dinv[i] * (double)ri) : ri;
-        r[i] = ri;
-        rr += (double)ri * (double)ri;
-        rz += (double)ri * (double)zi;
+    for (; i0 < e; i0 += UB * VB) {
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int64_t i = i0 + j * VB;
+            if (i < e) {
+                const R ri = (R)((double)rv[j] - alpha * (double)qv[j]);
+                const R zi = dinv ? (R)((double)dv[j] * (double)ri) : ri;
+                r[i] = ri;
+                rr += (double)ri * (double)ri;
+                rz += (double)ri * (double)zi;
+            }
+        }
+        // the next UB entries per thread
+#pragma unroll
+        for (int j = 0; j < UB; ++j) {
+            const int64_t i = i0 + UB * VB + j * VB;
+            const bool in = i < e;
+            rv[j] = in ? r[i] : R(0);
+            qv[j] = in ? q[i] : R(0);
+            dv[j] = in && dinv ? dinv[i] : R(1);
+        }
     }
     rr = block_sum(rr, red);
     rz = block_sum(rz, red);
