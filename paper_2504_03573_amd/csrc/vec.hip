@@ -7,7 +7,14 @@
 namespace sipdg {
 
 constexpr int VB = 256;   // threads per vector block
-constexpr int UB = 8;     // entries per thread whose loads are issued together
+// Entries per thread whose loads are issued together, by precision (FP64
+// vectors: 8; FP32: 4 in the updates, 1 in the dot product, which measured
+// fastest on the 32^3 workload and the 64-problem batch)
+template <class R>
+struct Ub {
+    static constexpr int UPD = sizeof(R) == 8 ? 8 : 4;
+    static constexpr int DOT = sizeof(R) == 8 ? 8 : 1;
+};
 
 __device__ inline double block_sum(double v, double *red) {
     red[threadIdx.x] = v;
@@ -29,6 +36,7 @@ __global__ __launch_bounds__(VB) void k_dot(VecCtx V, const R *a, const R *b, do
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
     double acc = 0.0;
     // UB entries per thread loaded before they are added (in the same order)
+    constexpr int UB = Ub<R>::DOT;
     for (int64_t i0 = s + threadIdx.x; i0 < e; i0 += UB * VB) {
         R av[UB], bv[UB];
 #pragma unroll
@@ -159,6 +167,7 @@ __global__ __launch_bounds__(VB) void k_update(VecCtx V, const CgScalars S, R *x
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
     const double alpha = block_alpha(V, S, ppq, prob, red);
     double rr = 0.0, rz = 0.0;
+    constexpr int UB = Ub<R>::UPD;
     for (int64_t i0 = s + threadIdx.x; i0 < e; i0 += UB * VB) {
         R xv[UB], pv[UB], rv[UB], qv[UB], dv[UB];
 #pragma unroll
@@ -206,6 +215,7 @@ __global__ __launch_bounds__(VB) void k_update_fold(VecCtx V, const CgScalars S,
     const int prob = V.blk_prob[blockIdx.x];
     const int64_t s = V.blk_start[blockIdx.x], e = V.blk_start[blockIdx.x + 1];
     // the first UB entries per thread are requested before alpha is formed
+    constexpr int UB = Ub<R>::UPD;
     int64_t i0 = s + threadIdx.x;
     R rv[UB], qv[UB], dv[UB];
 #pragma unroll
